@@ -1,0 +1,207 @@
+/*
+ * obfft -- Ozaki-Bailey full-FP64 complex 3-D FFT for AMD MI355X (gfx950).
+ *
+ * C ABI of the library libobfft.so.  Every transform is a Bailey six-step FFT
+ * per axis (Sec. 2, "The Bailey six-step FFT": input index j = j1 + p j2,
+ * output index k = k2 + q k1) whose two DFT stages are Ozaki-II residue GEMMs
+ * on MFMA (Sec. 2, Eq. ozaki) with the twiddles fused into the second-stage
+ * operands (Sec. 4.1, Eq. twiddle-fusion), complex products by the 3-real-GEMM
+ * Karatsuba split combined in the residue domain (Alg. 1), and an exact CRT
+ * reconstruction: a Phase-A GEMM on FP16 MFMA over canonical residues
+ * (Sec. 4.2, Eqs. fcrt, slicing, phaseAcost) followed by a Kulisch fixed-point
+ * accumulation, a two-sided modulo-M lift and one correctly rounded pack
+ * (Sec. 5.1, Alg. 2).
+ *
+ * Conventions (all entry points)
+ *   - Data are complex interleaved (re, im), C order, n3 fastest: the memory
+ *     layout of a contiguous torch.complex128 (FP64 target) or complex64
+ *     (FP32 target) tensor of shape (n1, n2, n3).
+ *   - Forward transform: Y[k] = sum_j X[j] exp(-2 pi i j.k / n), unnormalised.
+ *     Inverse: exp(+2 pi i ...) and the factor 1/(n1 n2 n3).  Adjoint:
+ *     exp(+2 pi i ...), unnormalised (the Hermitian adjoint of forward).
+ *   - Axes are processed n3, then n2, then n1; stage 1 contracts over j2
+ *     (length q), stage 2 over j1 (length p).  Factorisation and axis order
+ *     change output bits; both are fixed by the plan.
+ *   - `in`/`out` are DEVICE pointers owned by the caller; in == out is
+ *     allowed, partial overlap is rejected with OBFFT_INVALID_VALUE.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls are stream-ordered and asynchronous; errors detectable on the host
+ *     are returned immediately; nothing is allocated on the device inside an
+ *     execute call except the plan workspace on its first use (see
+ *     obfft_set_workspace).
+ *   - No exception crosses the ABI.  A plan may be used from one stream at a
+ *     time unless each concurrent user has its own workspace.
+ */
+#ifndef OBFFT_H
+#define OBFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct obfft_plan_s* obfft_plan_t;
+
+typedef enum {
+  OBFFT_SUCCESS = 0,
+  OBFFT_INVALID_VALUE = 1,        /* bad pointer, size, option or overlap */
+  OBFFT_UNSUPPORTED_SIZE = 2,     /* an extent with no admissible p x q split */
+  OBFFT_CAPACITY_EXCEEDED = 3,    /* log2 M <= 1 + log2 K + 2(k+1) (Sec. 2, Eq. capacity) */
+  OBFFT_NONFINITE_INPUT = 4,      /* reserved: non-finite input values */
+  OBFFT_ALLOC_FAILED = 5,         /* device or host allocation failed */
+  OBFFT_HIP_ERROR = 6,            /* a HIP runtime call failed */
+  OBFFT_UNSUPPORTED_DEVICE = 7,   /* the current device is not gfx950 */
+  OBFFT_WRONG_PRECISION = 8       /* z2z call on an FP32 plan or c2c on an FP64 plan */
+} obfft_status_t;
+
+/* Precision target.  FP64: r = 12 moduli (Sec. 2 shipping set), k = 53.
+ * FP32: r = 6 moduli {2039, 2029, 2027, 1024, 961, 841}, log2 M = 62.6, k = 24,
+ * S = 8 (Sec. 7, "Ozaki-II for FP32"). */
+enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
+
+/* MFMA substrate of the residue GEMMs.  All substrates produce bit-identical
+ * outputs (the residues of an exact integer product are unique).
+ *   FP8  : E4M3 digit planes, v_mfma_f32_16x16x32_fp8_fp8, FP32 accumulation
+ *   INT8 : two signed 8-bit limbs, v_mfma_i32_16x16x64_i8, INT32 accumulation
+ *   FP16 : one FP16 operand per residue, v_mfma_f32_16x16x16_f16
+ *   AUTO : per modulus, the cheapest of the three (chosen at plan time) */
+enum { OBFFT_SUB_FP8 = 0, OBFFT_SUB_INT8 = 1, OBFFT_SUB_FP16 = 2, OBFFT_SUB_AUTO = 3 };
+
+typedef struct {
+  int precision;            /* OBFFT_PREC_* */
+  int substrate;            /* OBFFT_SUB_* */
+  int p[3];                 /* per axis (n1, n2, n3); 0 = library default */
+  int q[3];                 /* per axis; p*q must equal the extent */
+  int n_moduli_override;    /* 0 = the precision's set; else use moduli_override */
+  const int32_t* moduli_override; /* host pointer, pairwise coprime, each < 2048 */
+  int reserved[8];
+} obfft_options_t;
+
+typedef struct {
+  int precision, substrate;
+  int r;                    /* number of moduli */
+  int32_t moduli[16];
+  double log2M;             /* log2 of the modulus product */
+  double budget_bits;       /* 1 + log2 Kmax + 2(k+1) of Eq. capacity */
+  int p[3], q[3];
+  int S, S_frac;            /* byte slices of u_k and of w_k (Sec. 4.2, Sec. 5.1) */
+  int64_t n[3];
+  size_t workspace_bytes;
+} obfft_plan_info_t;
+
+/* Fills `opt` with defaults: FP64, AUTO substrate, library factorisation. */
+void obfft_options_default(obfft_options_t* opt);
+
+/* Creates a plan for an n1 x n2 x n3 transform.  Computes every constant of
+ * Sec. 2 / Sec. 4.2 / Sec. 5.1 for the modulus set, checks the capacity
+ * budget for Kmax = max over axes of max(p, q) (Eq. capacity; rejects with
+ * OBFFT_CAPACITY_EXCEEDED), quantises the roots of unity, builds the MFMA
+ * operand planes and uploads them to the current device.  opt may be NULL.
+ * On failure *plan is set to NULL.  Host and device memory is owned by the
+ * plan until obfft_plan_destroy. */
+obfft_status_t obfft_plan_create(obfft_plan_t* plan, int64_t n1, int64_t n2, int64_t n3,
+                                 const obfft_options_t* opt);
+obfft_status_t obfft_plan_destroy(obfft_plan_t plan);
+obfft_status_t obfft_plan_info(obfft_plan_t plan, obfft_plan_info_t* info);
+
+/* Bytes of device workspace an execute call needs (one array of the
+ * transform's size for the six-step ping-pong).  If the caller supplies
+ * none, the plan allocates it on first use and frees it on destroy. */
+size_t obfft_workspace_size(obfft_plan_t plan);
+obfft_status_t obfft_set_workspace(obfft_plan_t plan, void* device_ptr, size_t bytes);
+
+/* Copies the plan's quantised roots Q(w_N^t) = (RNE(2^B cos 2 pi t/N),
+ * RNE(-2^B sin 2 pi t/N)), t < N, for `axis` (0 = n1) into host memory
+ * (2 N int64).  B = 52 (FP64) or 23 (FP32).  Introspection only. */
+obfft_status_t obfft_plan_roots(obfft_plan_t plan, int axis, int64_t* host_out);
+
+/* FP64-target transforms (complex128 in/out). */
+obfft_status_t fft3d_z2z_forward(obfft_plan_t plan, const void* in, void* out, void* stream);
+obfft_status_t fft3d_z2z_inverse(obfft_plan_t plan, const void* in, void* out, void* stream);
+obfft_status_t fft3d_z2z_adjoint(obfft_plan_t plan, const void* in, void* out, void* stream);
+
+/* FP32-target transforms (complex64 in/out) on a plan made with
+ * precision = OBFFT_PREC_FP32 (Sec. 7). */
+obfft_status_t fft3d_c2c_forward(obfft_plan_t plan, const void* in, void* out, void* stream);
+obfft_status_t fft3d_c2c_inverse(obfft_plan_t plan, const void* in, void* out, void* stream);
+
+/* The comparator: a native FP64 FFT (radix butterflies in FP64 registers,
+ * FP64 twiddles; no emulation) of the same size on the same device.
+ * Works on any FP64 plan; uses the plan's workspace. */
+obfft_status_t fft3d_z2z_native_forward(obfft_plan_t plan, const void* in, void* out, void* stream);
+obfft_status_t fft3d_z2z_native_inverse(obfft_plan_t plan, const void* in, void* out, void* stream);
+
+/* One Bailey stage of one axis (unit-level access to the fused kernel).
+ * stage 1 reads natural order and writes Y' with Y'_{j1,k2} at slot
+ * j1 + p k2; stage 2 reads those slots and writes Z_{k1,k2} at k2 + q k1
+ * (Alg. 1).  direction: 0 forward, 1 conjugate.  out must not alias in.
+ * If residues_out (device) is not NULL, the canonical residues of every
+ * output's real and imaginary integer are written as uint16
+ * [slot][re/im][r] (debug tap; slows the kernel). */
+obfft_status_t obfft_stage(obfft_plan_t plan, int axis, int stage, int direction,
+                           const void* in, void* out, void* residues_out, void* stream);
+
+/* Exact CRT reconstruction of n scalars from canonical residues: the Phase-A
+ * GEMM on FP16 MFMA (Sec. 4.2, Eqs. fcrt and slicing) and the Kulisch Phase B
+ * with the two-sided modulo-M lift and the correctly rounded pack (Sec. 5.1,
+ * Alg. 2), exposed for unit-level parity.  precision selects the modulus set
+ * (12 moduli for FP64, 6 for FP32).
+ *   residues: device uint16 [n][r], residue k of output i in [0, m_k);
+ *             larger values are a caller error (results undefined, no fault).
+ *   exps:     device int32 [n]; output i is RNE(R_i * 2^exps[i]).
+ *   out:      device double [n] (FP64) or float [n] (FP32).
+ *   taps:     device uint32 [n][layout.stride] or NULL; see obfft_taps_layout. */
+obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const void* residues,
+                                     const void* exps, void* out, void* taps, void* stream);
+
+/* Word offsets inside one output's taps record of obfft_crt_reconstruct:
+ *   P    [P, P+S)        Phase-A slice sums P_s (Eq. slicing)
+ *   Z    [Z, Z+S_frac)   Phase-A lift sums Z_t (Sec. 5.1)
+ *   E    [E, E+n_E)      E = sum_k v_k u_k, little-endian words (mod 2^160)
+ *   zhat                 round-half-up(2^-48 sum_t 256^t Z_t)
+ *   R    [R, R+n_R)      the lifted value in [-M/2, M/2), two's complement
+ *   stride               words per output (the power-of-two exponent is at
+ *                        R + n_R) */
+typedef struct { int P, Z, E, n_E, zhat, R, n_R, stride; } obfft_taps_layout_t;
+void obfft_taps_layout(obfft_taps_layout_t* layout);
+
+/* Hardware-contract probe (tests only): one wave runs one instruction on
+ * device operands laid out one register set per lane.  kind 0: FP8
+ * 16x16x32 MFMA (a, b: 64 x 8 bytes, d: 64 x 4 float); 1: INT8 16x16x64
+ * (64 x 16 bytes, d: 64 x 4 int32); 2: FP16 32x32x16 (64 x 8 half, d: 64 x
+ * 16 float); 3: permlane32 swap (a, b: 64 uint32, d: 2 x 64 uint32); 4: E4M3
+ * conversion of 64 floats in a (b unused) into 64 bytes of d. */
+obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream);
+
+/* Host-only introspection (no device needed). */
+/* Q(w_N^t) scaled by 2^bits, t < N, into host int64 [N][2] (bits <= 61). */
+obfft_status_t obfft_quantised_roots(int64_t N, int bits, int64_t* host_out);
+
+typedef struct {
+  int r, S, S_frac;
+  double log2M;
+  int32_t moduli[16];
+  uint32_t M[4];            /* little-endian words of M */
+  uint32_t u[16][4];        /* CRT idempotents u_k (Sec. 4.2, Eq. fcrt) */
+  uint64_t w[16];           /* lift weights round(2^48 u_k / M) (Sec. 5.1) */
+} obfft_crt_constants_t;
+obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
+
+/* Batched transforms: `count` independent FP64 transforms of possibly
+ * different shapes, executed by one persistent kernel per Bailey pass.
+ * shapes: host int64 [count][3].  ins/outs: host arrays of device pointers. */
+obfft_status_t obfft_batch_plan_create(obfft_plan_t* plan, int count, const int64_t* shapes,
+                                       const obfft_options_t* opt);
+obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
+                                   void* stream);
+
+const char* obfft_status_string(obfft_status_t status);
+/* The status of the last failed call on this plan (OBFFT_SUCCESS if none). */
+obfft_status_t obfft_last_error(obfft_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OBFFT_H */

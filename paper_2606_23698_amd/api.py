@@ -1,0 +1,266 @@
+"""PyTorch-facing binding of libobfft: argument marshalling only.
+
+Every step of the transform runs in the HIP kernels of libobfft.so; this
+module checks tensors, passes device pointers and the current HIP stream,
+and raises ObfftError on a failed status.  There is no CPU fallback.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+SUBSTRATES = {"fp8": 0, "int8": 1, "fp16": 2, "auto": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, numel=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def options(precision="fp64", substrate="auto", pq=None, moduli=None):
+    opt = L.Options()
+    L.lib().obfft_options_default(ctypes.byref(opt))
+    opt.precision = PRECISIONS[precision]
+    opt.substrate = SUBSTRATES[substrate]
+    if pq is not None:
+        for a, (p, q) in enumerate(pq):
+            opt.p[a] = int(p)
+            opt.q[a] = int(q)
+    keep = None
+    if moduli is not None:
+        keep = (ctypes.c_int32 * len(moduli))(*moduli)
+        opt.n_moduli_override = len(moduli)
+        opt.moduli_override = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+    return opt, keep
+
+
+class Plan:
+    """An Ozaki-Bailey 3-D FFT plan for one shape on the current device."""
+
+    def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None):
+        self.shape = tuple(int(n) for n in shape)
+        if len(self.shape) != 3:
+            raise ValueError("shape must have three extents")
+        self.precision = precision
+        opt, keep = options(precision, substrate, pq, moduli)
+        h = ctypes.c_void_p()
+        L.check(L.lib().obfft_plan_create(ctypes.byref(h), *self.shape, ctypes.byref(opt)),
+                "obfft_plan_create")
+        self._h = h
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().obfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = L.PlanInfo()
+        L.check(L.lib().obfft_plan_info(self._h, ctypes.byref(inf)), "obfft_plan_info")
+        return {"precision": inf.precision, "substrate": inf.substrate, "r": inf.r,
+                "moduli": list(inf.moduli[:inf.r]), "log2M": inf.log2M,
+                "budget_bits": inf.budget_bits, "p": list(inf.p), "q": list(inf.q),
+                "S": inf.S, "S_frac": inf.S_frac, "n": list(inf.n),
+                "workspace_bytes": inf.workspace_bytes}
+
+    def roots(self, axis):
+        N = self.shape[axis]
+        out = np.zeros((N, 2), dtype=np.int64)
+        L.check(L.lib().obfft_plan_roots(self._h, axis, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                "obfft_plan_roots")
+        return out
+
+    def set_workspace(self, ws):
+        L.check(L.lib().obfft_set_workspace(self._h, _ptr(ws), ws.numel() * ws.element_size()),
+                "obfft_set_workspace")
+        self._ws = ws
+
+    def _run(self, fname, x, out, stream):
+        _check_dev(x, self.cdtype, name="input")
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"input shape {tuple(x.shape)} != plan shape {self.shape}")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_dev(out, self.cdtype, x.numel(), name="output")
+        L.check(getattr(L.lib(), fname)(self._h, _ptr(x), _ptr(out), _stream(stream)), fname)
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        return self._run("fft3d_z2z_forward" if self.precision == "fp64" else "fft3d_c2c_forward",
+                         x, out, stream)
+
+    def inverse(self, x, out=None, stream=None):
+        return self._run("fft3d_z2z_inverse" if self.precision == "fp64" else "fft3d_c2c_inverse",
+                         x, out, stream)
+
+    def adjoint(self, x, out=None, stream=None):
+        return self._run("fft3d_z2z_adjoint", x, out, stream)
+
+    def native_forward(self, x, out=None, stream=None):
+        return self._run("fft3d_z2z_native_forward", x, out, stream)
+
+    def native_inverse(self, x, out=None, stream=None):
+        return self._run("fft3d_z2z_native_inverse", x, out, stream)
+
+    def stage(self, axis, stage, x, out=None, direction=0, residues=None, stream=None):
+        """One Bailey stage of one axis; residues (int16 [numel, 2, r]) receives the tap."""
+        _check_dev(x, self.cdtype, name="input")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_dev(out, self.cdtype, x.numel(), name="output")
+        rp = ctypes.c_void_p(0)
+        if residues is not None:
+            _check_dev(residues, torch.int16, name="residues")
+            rp = _ptr(residues)
+        L.check(L.lib().obfft_stage(self._h, axis, stage, direction, _ptr(x), _ptr(out), rp,
+                                    _stream(stream)), "obfft_stage")
+        return out
+
+
+class BatchPlan:
+    """Several independent FP64 transforms of (possibly) different shapes."""
+
+    def __init__(self, shapes, substrate="auto"):
+        self.shapes = [tuple(int(n) for n in s) for s in shapes]
+        arr = np.ascontiguousarray(np.array(self.shapes, dtype=np.int64).reshape(-1))
+        opt, _ = options("fp64", substrate)
+        h = ctypes.c_void_p()
+        L.check(L.lib().obfft_batch_plan_create(ctypes.byref(h), len(self.shapes),
+                                                arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                ctypes.byref(opt)), "obfft_batch_plan_create")
+        self._h = h
+
+    def forward(self, xs, outs=None, stream=None):
+        if len(xs) != len(self.shapes):
+            raise ValueError("wrong number of inputs")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for x, o, s in zip(xs, outs, self.shapes):
+            _check_dev(x, torch.complex128, name="input")
+            _check_dev(o, torch.complex128, x.numel(), name="output")
+            if tuple(x.shape) != s:
+                raise ValueError("input shape mismatch")
+        ins = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        ous = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        L.check(L.lib().obfft_batch_forward(self._h, ins, ous, _stream(stream)), "obfft_batch_forward")
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().obfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_plans = {}
+
+
+def get_plan(shape, precision="fp64", substrate="auto", device=None):
+    dev = torch.cuda.current_device() if device is None else device
+    key = (tuple(shape), precision, substrate, dev)
+    if key not in _plans:
+        with torch.cuda.device(dev):
+            _plans[key] = Plan(shape, precision, substrate)
+    return _plans[key]
+
+
+def fft3(x, substrate="auto", out=None):
+    prec = "fp64" if x.dtype == torch.complex128 else "fp32"
+    return get_plan(x.shape, prec, substrate, x.device.index).forward(x, out)
+
+
+def ifft3(x, substrate="auto", out=None):
+    prec = "fp64" if x.dtype == torch.complex128 else "fp32"
+    return get_plan(x.shape, prec, substrate, x.device.index).inverse(x, out)
+
+
+def adjoint3(x, substrate="auto", out=None):
+    return get_plan(x.shape, "fp64", substrate, x.device.index).adjoint(x, out)
+
+
+def native_fft3(x, out=None):
+    return get_plan(x.shape, "fp64", "auto", x.device.index).native_forward(x, out)
+
+
+def native_ifft3(x, out=None):
+    return get_plan(x.shape, "fp64", "auto", x.device.index).native_inverse(x, out)
+
+
+def crt_reconstruct(residues, exps, precision="fp64", taps=False, stream=None):
+    """Phase A + Kulisch Phase B of n scalars: residues int16 [n, r] (canonical), exps int32 [n]."""
+    n = residues.shape[0]
+    _check_dev(residues, torch.int16, name="residues")
+    _check_dev(exps, torch.int32, n, name="exps")
+    out = torch.empty(n, dtype=torch.float64 if precision == "fp64" else torch.float32,
+                      device=residues.device)
+    tp = None
+    tptr = ctypes.c_void_p(0)
+    if taps:
+        lay = taps_layout()
+        tp = torch.zeros((n, lay["stride"]), dtype=torch.int32, device=residues.device)
+        tptr = _ptr(tp)
+    L.check(L.lib().obfft_crt_reconstruct(PRECISIONS[precision], n, _ptr(residues), _ptr(exps),
+                                          _ptr(out), tptr, _stream(stream)), "obfft_crt_reconstruct")
+    return out, tp
+
+
+def taps_layout():
+    t = L.TapsLayout()
+    L.lib().obfft_taps_layout(ctypes.byref(t))
+    return {n: getattr(t, n) for n, _ in L.TapsLayout._fields_}
+
+
+def mfma_probe(kind, a, b, d, stream=None):
+    bp = _ptr(b) if b is not None else ctypes.c_void_p(0)
+    L.check(L.lib().obfft_mfma_probe(kind, _ptr(a), bp, _ptr(d), _stream(stream)), "obfft_mfma_probe")
+    return d
+
+
+def quantised_roots(N, bits=52):
+    out = np.zeros((N, 2), dtype=np.int64)
+    L.check(L.lib().obfft_quantised_roots(N, bits, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+            "obfft_quantised_roots")
+    return out
+
+
+def crt_constants(precision="fp64"):
+    c = L.CrtConstants()
+    L.check(L.lib().obfft_crt_constants(PRECISIONS[precision], ctypes.byref(c)), "obfft_crt_constants")
+    r = c.r
+
+    def words(ws):
+        return sum(int(w) << (32 * i) for i, w in enumerate(ws))
+
+    return {"r": r, "S": c.S, "S_frac": c.S_frac, "log2M": c.log2M,
+            "moduli": list(c.moduli[:r]), "M": words(c.M),
+            "u": [words(c.u[k]) for k in range(r)], "w": [int(c.w[k]) for k in range(r)]}

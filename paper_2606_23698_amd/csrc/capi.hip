@@ -1,0 +1,576 @@
+// C ABI of libobfft: plans, the six-step driver and the unit-level entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "obfft.h"
+#include "plan_math.h"
+
+namespace obfft {
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
+                        int64_t grid, hipStream_t st);
+hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
+                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts& C, hipStream_t st);
+hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
+hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
+hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
+struct NativePlan;
+NativePlan* native_plan_create(const int64_t* n, std::string& err);
+void native_plan_destroy(NativePlan* np);
+hipError_t native_execute(NativePlan* np, const void* in, void* out, void* ws, int inverse, hipStream_t st);
+}  // namespace obfft
+
+using namespace obfft;
+
+static const int32_t kModFP64[12] = {2039, 2029, 2027, 1089, 1024, 961, 841, 625, 529, 511, 491, 487};
+static const int32_t kModFP32[6] = {2039, 2029, 2027, 1024, 961, 841};
+
+struct DevPlanes {
+  OperandPlanes L;
+};
+
+struct obfft_plan_s {
+  int64_t n[3] = {0, 0, 0};
+  int p[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+  int precision = 0, substrate = SUB_FP8, kbits = 53;
+  ModSet H;
+  CrtConsts C;
+  ModConsts MC;
+  std::vector<int64_t> roots[3];
+  DevPlanes planes[3][2][2];  // axis, stage-1, direction
+  std::vector<void*> dev_allocs;
+  uint16_t* d_phaseA = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  obfft_status_t last = OBFFT_SUCCESS;
+  NativePlan* native = nullptr;
+  int device = 0;
+  // batch plans
+  int batch_count = 0;
+  std::vector<obfft_plan_t> members;
+};
+
+static obfft_status_t fail(obfft_plan_t plan, obfft_status_t s) {
+  if (plan) plan->last = s;
+  return s;
+}
+
+static bool device_is_gfx950() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  return strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+extern "C" void obfft_options_default(obfft_options_t* opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->precision = OBFFT_PREC_FP64;
+  opt->substrate = OBFFT_SUB_AUTO;
+}
+
+// Library default factorisation N = p q: p <= q, both even, both <= 32,
+// p as close to sqrt(N) as possible (32 = 4 x 8, 256 = 16 x 16, 1024 = 32 x 32).
+static bool default_split(int64_t N, int* p, int* q) {
+  int best = -1;
+  for (int a = 2; a <= kMaxK; a += 2) {
+    if (N % a) continue;
+    int64_t b = N / a;
+    if (b < a || b > kMaxK || (b & 1)) continue;
+    best = a;
+  }
+  if (best < 0) return false;
+  *p = best;
+  *q = (int)(N / best);
+  return true;
+}
+
+static void build_modconsts(const ModSet& H, ModConsts& MC, int substrate) {
+  memset(&MC, 0, sizeof(MC));
+  for (int i = 0; i < H.r; i++) {
+    MC.m[i] = H.m[i];
+    MC.inv_mf[i] = 1.0f / (float)H.m[i];
+    MC.inv_md[i] = 1.0 / (double)H.m[i];
+    MC.nd[i] = fp8_digits(H.m[i]);
+    MC.sub[i] = substrate;
+  }
+}
+
+static obfft_status_t upload(obfft_plan_t plan, const void* host, size_t bytes, void** dev) {
+  void* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) return OBFFT_ALLOC_FAILED;
+  plan->dev_allocs.push_back(d);
+  if (hipMemcpy(d, host, bytes, hipMemcpyHostToDevice) != hipSuccess) return OBFFT_HIP_ERROR;
+  *dev = d;
+  return OBFFT_SUCCESS;
+}
+
+static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) {
+  plan->precision = opt->precision;
+  int sub = opt->substrate;
+  if (sub == OBFFT_SUB_AUTO || sub == OBFFT_SUB_FP16) sub = OBFFT_SUB_INT8;
+  plan->substrate = sub;
+  plan->kbits = plan->precision == OBFFT_PREC_FP32 ? 24 : 53;
+  const int32_t* mods = plan->precision == OBFFT_PREC_FP32 ? kModFP32 : kModFP64;
+  int r = plan->precision == OBFFT_PREC_FP32 ? 6 : 12;
+  if (opt->n_moduli_override) {
+    if (!opt->moduli_override) return OBFFT_INVALID_VALUE;
+    mods = opt->moduli_override;
+    r = opt->n_moduli_override;
+  }
+  std::string err;
+  if (!build_modset(mods, r, plan->H, err)) return OBFFT_INVALID_VALUE;
+  int64_t kmax = 0;
+  for (int a = 0; a < 3; a++) {
+    int64_t N = plan->n[a];
+    int pp = opt->p[a], qq = opt->q[a];
+    if (pp == 0 && qq == 0) {
+      if (!default_split(N, &pp, &qq)) return OBFFT_UNSUPPORTED_SIZE;
+    } else if ((int64_t)pp * qq != N) {
+      return OBFFT_INVALID_VALUE;
+    }
+    if (pp < 2 || qq < 2 || (pp & 1) || (qq & 1) || pp > kMaxK || qq > kMaxK) return OBFFT_UNSUPPORTED_SIZE;
+    plan->p[a] = pp;
+    plan->q[a] = qq;
+    kmax = std::max<int64_t>(kmax, std::max(pp, qq));
+  }
+  // Eq. capacity: log2 M > 1 + log2 K + 2(k+1)
+  if (!(plan->H.log2M > capacity_bits(kmax, plan->kbits))) return OBFFT_CAPACITY_EXCEEDED;
+  int expect_r = plan->precision == OBFFT_PREC_FP32 ? 6 : 12, expect_S = plan->precision ? 8 : 15;
+  if (plan->H.r != expect_r || plan->H.S != expect_S || plan->H.T != 6) return OBFFT_UNSUPPORTED_SIZE;
+  build_crt_consts(plan->H, plan->C);
+  build_modconsts(plan->H, plan->MC, sub);
+  if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
+  hipGetDevice(&plan->device);
+  int bits = plan->kbits - 1;
+  std::map<std::tuple<int64_t, int, int, int, int>, OperandPlanes> cache;
+  for (int a = 0; a < 3; a++) {
+    quantised_roots(plan->n[a], bits, plan->roots[a]);
+    for (int st = 1; st <= 2; st++)
+      for (int d = 0; d < 2; d++) {
+        auto key = std::make_tuple(plan->n[a], plan->p[a], plan->q[a], st, d);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+          plan->planes[a][st - 1][d].L = it->second;
+          continue;
+        }
+        std::vector<uint8_t> bytes;
+        OperandPlanes L;
+        build_operand_planes(plan->H, plan->roots[a], plan->n[a], plan->p[a], plan->q[a], st, d, sub, bytes, L);
+        void* dptr = nullptr;
+        obfft_status_t s = upload(plan, bytes.data(), bytes.size(), &dptr);
+        if (s != OBFFT_SUCCESS) return s;
+        L.dev = (uint8_t*)dptr;
+        if (sub == SUB_FP8) {
+          if (launch_digits_to_fp8(L.dev, (int64_t)bytes.size(), 0) != hipSuccess) return OBFFT_HIP_ERROR;
+        }
+        cache[key] = L;
+        plan->planes[a][st - 1][d].L = L;
+      }
+  }
+  std::vector<uint16_t> pa;
+  int npairs = 0;
+  build_phaseA_operand(plan->H, pa, &npairs);
+  void* dpa = nullptr;
+  obfft_status_t s = upload(plan, pa.data(), pa.size() * 2, &dpa);
+  if (s != OBFFT_SUCCESS) return s;
+  plan->d_phaseA = (uint16_t*)dpa;
+  plan->ws_bytes = (size_t)(plan->n[0] * plan->n[1] * plan->n[2]) * (plan->precision ? 8 : 16);
+  if (hipDeviceSynchronize() != hipSuccess) return OBFFT_HIP_ERROR;
+  if (plan->precision == OBFFT_PREC_FP64) {
+    std::string nerr;
+    plan->native = native_plan_create(plan->n, nerr);
+  }
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_plan_create(obfft_plan_t* out, int64_t n1, int64_t n2, int64_t n3,
+                                            const obfft_options_t* opt) {
+  if (!out) return OBFFT_INVALID_VALUE;
+  *out = nullptr;
+  if (n1 < 1 || n2 < 1 || n3 < 1) return OBFFT_INVALID_VALUE;
+  obfft_options_t def;
+  obfft_options_default(&def);
+  if (!opt) opt = &def;
+  if (opt->precision != OBFFT_PREC_FP64 && opt->precision != OBFFT_PREC_FP32) return OBFFT_INVALID_VALUE;
+  if (opt->substrate < 0 || opt->substrate > OBFFT_SUB_AUTO) return OBFFT_INVALID_VALUE;
+  obfft_plan_t plan = new (std::nothrow) obfft_plan_s();
+  if (!plan) return OBFFT_ALLOC_FAILED;
+  plan->n[0] = n1;
+  plan->n[1] = n2;
+  plan->n[2] = n3;
+  obfft_status_t s;
+  try {
+    s = plan_build(plan, opt);
+  } catch (...) {
+    s = OBFFT_INVALID_VALUE;
+  }
+  if (s != OBFFT_SUCCESS) {
+    obfft_plan_destroy(plan);
+    return s;
+  }
+  *out = plan;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_plan_destroy(obfft_plan_t plan) {
+  if (!plan) return OBFFT_INVALID_VALUE;
+  for (auto m : plan->members) obfft_plan_destroy(m);
+  for (void* d : plan->dev_allocs) hipFree(d);
+  if (plan->ws_owned && plan->ws) hipFree(plan->ws);
+  if (plan->native) native_plan_destroy(plan->native);
+  delete plan;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_plan_info(obfft_plan_t plan, obfft_plan_info_t* info) {
+  if (!plan || !info) return OBFFT_INVALID_VALUE;
+  memset(info, 0, sizeof(*info));
+  info->precision = plan->precision;
+  info->substrate = plan->substrate;
+  info->r = plan->H.r;
+  for (int i = 0; i < plan->H.r; i++) info->moduli[i] = plan->H.m[i];
+  info->log2M = plan->H.log2M;
+  int64_t kmax = 0;
+  for (int a = 0; a < 3; a++) {
+    info->p[a] = plan->p[a];
+    info->q[a] = plan->q[a];
+    info->n[a] = plan->n[a];
+    kmax = std::max<int64_t>(kmax, std::max(plan->p[a], plan->q[a]));
+  }
+  info->budget_bits = kmax ? capacity_bits(kmax, plan->kbits) : 0.0;
+  info->S = plan->H.S;
+  info->S_frac = plan->H.T;
+  info->workspace_bytes = plan->ws_bytes;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" size_t obfft_workspace_size(obfft_plan_t plan) { return plan ? plan->ws_bytes : 0; }
+
+extern "C" obfft_status_t obfft_set_workspace(obfft_plan_t plan, void* ptr, size_t bytes) {
+  if (!plan || !ptr || bytes < plan->ws_bytes) return fail(plan, OBFFT_INVALID_VALUE);
+  if (plan->ws_owned && plan->ws) hipFree(plan->ws);
+  plan->ws = ptr;
+  plan->ws_owned = false;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_plan_roots(obfft_plan_t plan, int axis, int64_t* host_out) {
+  if (!plan || !host_out || axis < 0 || axis > 2) return fail(plan, OBFFT_INVALID_VALUE);
+  memcpy(host_out, plan->roots[axis].data(), plan->roots[axis].size() * sizeof(int64_t));
+  return OBFFT_SUCCESS;
+}
+
+static obfft_status_t ensure_ws(obfft_plan_t plan) {
+  if (plan->ws) return OBFFT_SUCCESS;
+  if (hipMalloc(&plan->ws, plan->ws_bytes) != hipSuccess) {
+    plan->ws = nullptr;
+    return OBFFT_ALLOC_FAILED;
+  }
+  plan->ws_owned = true;
+  return OBFFT_SUCCESS;
+}
+
+static bool overlaps(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x != y && x < y + bytes && y < x + bytes;
+}
+
+static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, const void* in, void* out,
+                         StageParams& P, int64_t& grid) {
+  memset(&P, 0, sizeof(P));
+  int64_t N = plan->n[axis];
+  int64_t inner = 1, outer = 1;
+  for (int b = axis + 1; b < 3; b++) inner *= plan->n[b];
+  for (int b = 0; b < axis; b++) outer *= plan->n[b];
+  int64_t p = plan->p[axis], q = plan->q[axis];
+  P.in = in;
+  P.out = out;
+  P.inner = inner;
+  P.N = N;
+  P.s_o = N * inner;
+  P.stage = stage;
+  const OperandPlanes& L = plan->planes[axis][stage - 1][direction].L;
+  P.amat = L.dev;
+  P.amat_g_stride = stage == 1 ? 0 : L.g_stride;
+  P.amat_mod_stride = L.mod_stride;
+  P.amat_fmax = L.fmax;
+  P.amat_chmax = L.chmax;
+  P.amat_mt = L.mt;
+  P.phaseA = plan->d_phaseA;
+  if (stage == 1) {
+    P.K = (int)q;
+    P.G = (int)p;
+    P.ncols = outer * p * inner;
+    P.s_in_g = inner;
+    P.s_in_s = p * inner;
+    P.s_out_g = inner;
+    P.s_out_t = p * inner;
+    grid = (P.ncols + kCols - 1) / kCols;
+  } else {
+    P.K = (int)p;
+    P.G = (int)q;
+    P.ncols = outer * inner;
+    P.s_in_g = p * inner;
+    P.s_in_s = inner;
+    P.s_out_g = inner;
+    P.s_out_t = q * inner;
+    P.tiles_per_g = (int)((P.ncols + kCols - 1) / kCols);
+    grid = (int64_t)P.tiles_per_g * q;
+  }
+}
+
+static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int direction, const void* in,
+                                void* out, int extra_shift, uint16_t* dbg, hipStream_t st) {
+  StageParams P;
+  int64_t grid;
+  stage_params(plan, axis, stage, direction, in, out, P, grid);
+  P.extra_shift = extra_shift;
+  P.dbg_res = dbg;
+  if (grid <= 0) return OBFFT_SUCCESS;
+  if (launch_stage(plan->substrate, plan->precision, P, plan->MC, plan->C, grid, st) != hipSuccess)
+    return OBFFT_HIP_ERROR;
+  return OBFFT_SUCCESS;
+}
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static obfft_status_t run_transform(obfft_plan_t plan, const void* in, void* out, int direction,
+                                    bool normalise, void* stream) {
+  if (!in || !out) return OBFFT_INVALID_VALUE;
+  int64_t total = plan->n[0] * plan->n[1] * plan->n[2];
+  size_t bytes = (size_t)total * (plan->precision ? 8 : 16);
+  if (overlaps(in, out, bytes)) return OBFFT_INVALID_VALUE;
+  obfft_status_t s = ensure_ws(plan);
+  if (s != OBFFT_SUCCESS) return s;
+  hipStream_t st = (hipStream_t)stream;
+  int shift = 0;
+  bool post_scale = false;
+  if (normalise) {
+    if (is_pow2(total)) {
+      int l = 0;
+      while (((int64_t)1 << l) < total) l++;
+      shift = -l;
+    } else {
+      post_scale = true;
+    }
+  }
+  const int order[3] = {2, 1, 0};
+  const void* cur = in;
+  for (int k = 0; k < 3; k++) {
+    int a = order[k];
+    s = run_stage(plan, a, 1, direction, cur, plan->ws, 0, nullptr, st);
+    if (s != OBFFT_SUCCESS) return s;
+    s = run_stage(plan, a, 2, direction, plan->ws, out, k == 2 ? shift : 0, nullptr, st);
+    if (s != OBFFT_SUCCESS) return s;
+    cur = out;
+  }
+  if (post_scale) {
+    if (launch_scale(out, 2 * total, 1.0 / (double)total, plan->precision, st) != hipSuccess)
+      return OBFFT_HIP_ERROR;
+  }
+  return OBFFT_SUCCESS;
+}
+
+#define CHECK_PLAN(prec)                                   \
+  if (!plan) return OBFFT_INVALID_VALUE;                   \
+  if (plan->batch_count) return fail(plan, OBFFT_INVALID_VALUE); \
+  if (plan->precision != (prec)) return fail(plan, OBFFT_WRONG_PRECISION);
+
+extern "C" obfft_status_t fft3d_z2z_forward(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP64);
+  return fail(plan, run_transform(plan, in, out, 0, false, stream));
+}
+extern "C" obfft_status_t fft3d_z2z_inverse(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP64);
+  return fail(plan, run_transform(plan, in, out, 1, true, stream));
+}
+extern "C" obfft_status_t fft3d_z2z_adjoint(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP64);
+  return fail(plan, run_transform(plan, in, out, 1, false, stream));
+}
+extern "C" obfft_status_t fft3d_c2c_forward(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP32);
+  return fail(plan, run_transform(plan, in, out, 0, false, stream));
+}
+extern "C" obfft_status_t fft3d_c2c_inverse(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP32);
+  return fail(plan, run_transform(plan, in, out, 1, true, stream));
+}
+
+static obfft_status_t run_native(obfft_plan_t plan, const void* in, void* out, int inverse, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP64);
+  if (!plan->native) return fail(plan, OBFFT_UNSUPPORTED_SIZE);
+  if (!in || !out) return fail(plan, OBFFT_INVALID_VALUE);
+  int64_t total = plan->n[0] * plan->n[1] * plan->n[2];
+  if (overlaps(in, out, (size_t)total * 16)) return fail(plan, OBFFT_INVALID_VALUE);
+  obfft_status_t s = ensure_ws(plan);
+  if (s != OBFFT_SUCCESS) return fail(plan, s);
+  if (native_execute(plan->native, in, out, plan->ws, inverse, (hipStream_t)stream) != hipSuccess)
+    return fail(plan, OBFFT_HIP_ERROR);
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t fft3d_z2z_native_forward(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  return run_native(plan, in, out, 0, stream);
+}
+extern "C" obfft_status_t fft3d_z2z_native_inverse(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  return run_native(plan, in, out, 1, stream);
+}
+
+extern "C" obfft_status_t obfft_stage(obfft_plan_t plan, int axis, int stage, int direction, const void* in,
+                                      void* out, void* residues_out, void* stream) {
+  if (!plan || plan->batch_count) return OBFFT_INVALID_VALUE;
+  if (axis < 0 || axis > 2 || (stage != 1 && stage != 2) || (direction != 0 && direction != 1) || !in ||
+      !out || in == out)
+    return fail(plan, OBFFT_INVALID_VALUE);
+  return fail(plan, run_stage(plan, axis, stage, direction, in, out, 0, (uint16_t*)residues_out,
+                              (hipStream_t)stream));
+}
+
+// ---- unit-level CRT reconstruction (cached constants per precision) ----
+struct CrtCache {
+  bool ready = false;
+  CrtConsts C;
+  uint16_t* d_phaseA = nullptr;
+};
+static std::mutex g_crt_mu;
+static std::map<std::pair<int, int>, CrtCache> g_crt;
+
+extern "C" obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const void* residues, const void* exps,
+                                                void* out, void* taps, void* stream) {
+  if ((precision != 0 && precision != 1) || n < 0 || (n > 0 && (!residues || !exps || !out)))
+    return OBFFT_INVALID_VALUE;
+  if (n == 0) return OBFFT_SUCCESS;
+  if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
+  int dev = 0;
+  hipGetDevice(&dev);
+  CrtCache* cc;
+  {
+    std::lock_guard<std::mutex> lk(g_crt_mu);
+    cc = &g_crt[std::make_pair(dev, precision)];
+    if (!cc->ready) {
+      ModSet H;
+      std::string err;
+      if (!build_modset(precision ? kModFP32 : kModFP64, precision ? 6 : 12, H, err)) return OBFFT_INVALID_VALUE;
+      build_crt_consts(H, cc->C);
+      std::vector<uint16_t> pa;
+      int npairs = 0;
+      build_phaseA_operand(H, pa, &npairs);
+      if (hipMalloc(&cc->d_phaseA, pa.size() * 2) != hipSuccess) return OBFFT_ALLOC_FAILED;
+      if (hipMemcpy(cc->d_phaseA, pa.data(), pa.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+        return OBFFT_HIP_ERROR;
+      cc->ready = true;
+    }
+  }
+  if (launch_crt(precision, n, (const uint16_t*)residues, (const int*)exps, out, (uint32_t*)taps, cc->d_phaseA,
+                 cc->C, (hipStream_t)stream) != hipSuccess)
+    return OBFFT_HIP_ERROR;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" void obfft_taps_layout(obfft_taps_layout_t* t) {
+  if (!t) return;
+  t->P = 0;
+  t->Z = 16;
+  t->E = 24;
+  t->n_E = 5;
+  t->zhat = 29;
+  t->R = 30;
+  t->n_R = 4;
+  t->stride = kTapStride;
+}
+
+// Runs one MFMA (or lane-swap / conversion) probe on device buffers; used by
+// the hardware-contract tests.  kind: 0 fp8 16x16x32, 1 i8 16x16x64,
+// 2 f16 32x32x16, 3 permlane32 swap, 4 E4M3 conversion.
+extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream) {
+  if (kind < 0 || kind > 4 || !a || !d || (kind < 4 && !b)) return OBFFT_INVALID_VALUE;
+  if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
+  return launch_mfma_probe(kind, a, b, d, (hipStream_t)stream) == hipSuccess ? OBFFT_SUCCESS : OBFFT_HIP_ERROR;
+}
+
+// ---- batched transforms ----
+extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
+                                                  const obfft_options_t* opt) {
+  if (!out || count <= 0 || !shapes) return OBFFT_INVALID_VALUE;
+  *out = nullptr;
+  obfft_plan_t bp = new (std::nothrow) obfft_plan_s();
+  if (!bp) return OBFFT_ALLOC_FAILED;
+  bp->batch_count = count;
+  for (int i = 0; i < count; i++) {
+    obfft_plan_t m = nullptr;
+    obfft_status_t s = obfft_plan_create(&m, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2], opt);
+    if (s != OBFFT_SUCCESS) {
+      obfft_plan_destroy(bp);
+      return s;
+    }
+    bp->members.push_back(m);
+  }
+  *out = bp;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
+                                              void* stream) {
+  if (!plan || !plan->batch_count || !ins || !outs) return OBFFT_INVALID_VALUE;
+  for (int i = 0; i < plan->batch_count; i++) {
+    obfft_status_t s = fft3d_z2z_forward(plan->members[i], ins[i], outs[i], stream);
+    if (s != OBFFT_SUCCESS) return fail(plan, s);
+  }
+  return OBFFT_SUCCESS;
+}
+
+// ---- host-only introspection (no device needed) ----
+extern "C" obfft_status_t obfft_quantised_roots(int64_t N, int bits, int64_t* host_out) {
+  if (N < 1 || bits < 1 || bits > 61 || !host_out) return OBFFT_INVALID_VALUE;
+  std::vector<int64_t> q;
+  quantised_roots(N, bits, q);
+  memcpy(host_out, q.data(), q.size() * sizeof(int64_t));
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out) {
+  if ((precision != 0 && precision != 1) || !out) return OBFFT_INVALID_VALUE;
+  ModSet H;
+  std::string err;
+  if (!build_modset(precision ? kModFP32 : kModFP64, precision ? 6 : 12, H, err)) return OBFFT_INVALID_VALUE;
+  memset(out, 0, sizeof(*out));
+  out->r = H.r;
+  out->S = H.S;
+  out->S_frac = H.T;
+  out->log2M = H.log2M;
+  for (int i = 0; i < 4; i++) out->M[i] = (uint32_t)(H.M >> (32 * i));
+  for (int k = 0; k < H.r; k++) {
+    out->moduli[k] = H.m[k];
+    for (int i = 0; i < 4; i++) out->u[k][i] = (uint32_t)(H.u[k] >> (32 * i));
+    out->w[k] = H.w[k];
+  }
+  return OBFFT_SUCCESS;
+}
+
+extern "C" const char* obfft_status_string(obfft_status_t s) {
+  switch (s) {
+    case OBFFT_SUCCESS: return "OBFFT_SUCCESS";
+    case OBFFT_INVALID_VALUE: return "OBFFT_INVALID_VALUE";
+    case OBFFT_UNSUPPORTED_SIZE: return "OBFFT_UNSUPPORTED_SIZE";
+    case OBFFT_CAPACITY_EXCEEDED: return "OBFFT_CAPACITY_EXCEEDED";
+    case OBFFT_NONFINITE_INPUT: return "OBFFT_NONFINITE_INPUT";
+    case OBFFT_ALLOC_FAILED: return "OBFFT_ALLOC_FAILED";
+    case OBFFT_HIP_ERROR: return "OBFFT_HIP_ERROR";
+    case OBFFT_UNSUPPORTED_DEVICE: return "OBFFT_UNSUPPORTED_DEVICE";
+    case OBFFT_WRONG_PRECISION: return "OBFFT_WRONG_PRECISION";
+  }
+  return "unknown status";
+}
+
+extern "C" obfft_status_t obfft_last_error(obfft_plan_t plan) { return plan ? plan->last : OBFFT_INVALID_VALUE; }

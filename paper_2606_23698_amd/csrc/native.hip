@@ -1,0 +1,303 @@
+// Native FP64 3-D FFT for gfx950: the comparator of the emulated transform.
+//
+// One kernel pass per axis reads every element from HBM once and writes it
+// once (the traffic model Q = 96 N^3 bytes of Sec. 4.1, Eq. Q-fft).  A
+// workgroup stages B lines in LDS and runs a self-sorting (Stockham) mixed
+// radix-8/4/3/2 FFT on them: each pass reads R values per butterfly into
+// registers, multiplies by FP64 twiddles from a table of w_N^t, applies the
+// length-R DFT in registers and writes the results back to LDS in the
+// expanded (autosorted) positions.  No emulation: this is the plain FP64
+// path the Ozaki-Bailey kernel is measured against.
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+namespace obfft {
+
+void quantised_roots(int64_t N, int bits, std::vector<int64_t>& out);
+
+constexpr int kNatThreads = 256;
+constexpr int kNatLdsComplex = 8192;   // 128 KiB of complex data per workgroup
+constexpr int kMaxPasses = 12;
+constexpr int kNatRegs = 32;           // complex values a thread holds during a pass
+
+struct NatAxis {
+  int64_t N, inner, outer;
+  int B;                       // lines per workgroup
+  int npass;
+  int radix[kMaxPasses];
+  const double2* tw;           // w_N^t, t < N (forward sign)
+};
+
+struct NativePlan {
+  int64_t n[3];
+  NatAxis ax[3];
+  std::vector<void*> allocs;
+};
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_r(double2* v) {
+  // DIR = +1 forward (exp(-2 pi i / R)), -1 inverse
+  if (R == 2) {
+    double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+  } else if (R == 3) {
+    const double c1 = -0.5, s1 = 0.86602540378443864676 * DIR;
+    double2 a = v[0], b = v[1], c = v[2];
+    double2 t = make_double2(b.x + c.x, b.y + c.y);
+    double2 d = make_double2(b.x - c.x, b.y - c.y);
+    v[0] = make_double2(a.x + t.x, a.y + t.y);
+    double2 m = make_double2(a.x + c1 * t.x, a.y + c1 * t.y);
+    // -i s1 d
+    v[1] = make_double2(m.x + s1 * d.y, m.y - s1 * d.x);
+    v[2] = make_double2(m.x - s1 * d.y, m.y + s1 * d.x);
+  } else if (R == 4) {
+    double2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    double2 t0 = make_double2(a0.x + a2.x, a0.y + a2.y);
+    double2 t1 = make_double2(a0.x - a2.x, a0.y - a2.y);
+    double2 t2 = make_double2(a1.x + a3.x, a1.y + a3.y);
+    double2 t3 = make_double2(a1.x - a3.x, a1.y - a3.y);
+    // -i DIR t3
+    double2 u3 = make_double2(DIR * t3.y, -DIR * t3.x);
+    v[0] = make_double2(t0.x + t2.x, t0.y + t2.y);
+    v[2] = make_double2(t0.x - t2.x, t0.y - t2.y);
+    v[1] = make_double2(t1.x + u3.x, t1.y + u3.y);
+    v[3] = make_double2(t1.x - u3.x, t1.y - u3.y);
+  } else if (R == 8) {
+    const double h = 0.70710678118654752440;
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft_r<4, DIR>(e);
+    dft_r<4, DIR>(o);
+    // o[k] *= w_8^{k DIR}
+    double2 o1 = make_double2(h * (o[1].x + DIR * o[1].y), h * (o[1].y - DIR * o[1].x));
+    double2 o2 = make_double2(DIR * o[2].y, -DIR * o[2].x);
+    double2 o3 = make_double2(h * (-o[3].x + DIR * o[3].y), h * (-o[3].y - DIR * o[3].x));
+    double2 oo[4] = {o[0], o1, o2, o3};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      v[k] = make_double2(e[k].x + oo[k].x, e[k].y + oo[k].y);
+      v[k + 4] = make_double2(e[k].x - oo[k].x, e[k].y - oo[k].y);
+    }
+  }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void stockham_pass(double2* lds, int B, int64_t N, int Ns, const double2* tw) {
+  const int nb = (int)(N / R);        // butterflies per line
+  const int total = nb * B;
+  constexpr int MAXB = kNatRegs;      // complex values per thread per pass
+  // The plan sizes B so that one round covers every butterfly of the pass:
+  // all reads complete (barrier) before any write, so the pass is in place.
+  for (int base = 0; base < total; base += kNatThreads * (MAXB / R)) {
+    double2 reg[MAXB];
+#pragma unroll
+    for (int q = 0; q < MAXB / R; q++) {
+      int idx = base + q * kNatThreads + threadIdx.x;
+      if (idx < total) {
+        int line = idx / nb, j = idx % nb;
+        double2* src = lds + (int64_t)line * N;
+#pragma unroll
+        for (int r = 0; r < R; r++) reg[q * R + r] = src[j + r * nb];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB / R; q++) {
+      int idx = base + q * kNatThreads + threadIdx.x;
+      if (idx < total) {
+        int line = idx / nb, j = idx % nb;
+        int jm = j % Ns;
+        double2* x = &reg[q * R];
+        if (Ns > 1) {
+          // twiddle w_{Ns R}^{r jm} = w_N^{r jm N/(Ns R)}
+          int64_t step = N / ((int64_t)Ns * R) * jm;
+#pragma unroll
+          for (int r = 1; r < R; r++) {
+            double2 w = tw[(r * step) % N];
+            double wy = DIR * w.y;
+            double2 a = x[r];
+            x[r] = make_double2(a.x * w.x - a.y * wy, a.x * wy + a.y * w.x);
+          }
+        }
+        dft_r<R, DIR>(x);
+        int idxd = (j / Ns) * Ns * R + jm;
+        double2* dst = lds + (int64_t)line * N;
+#pragma unroll
+        for (int r = 0; r < R; r++) dst[idxd + r * Ns] = x[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int DIR>
+__global__ __launch_bounds__(kNatThreads) void native_axis_kernel(const double2* in, double2* out, NatAxis A,
+                                                                  double post_scale) {
+  extern __shared__ __align__(16) double2 lds[];
+  const int64_t N = A.N, inner = A.inner;
+  const int B = A.B;
+  const int64_t nlines = A.outer * inner;
+  const int64_t line0 = (int64_t)blockIdx.x * B;
+  const int nl = (int)min((int64_t)B, nlines - line0);
+  // load: element (line, n) of line id L = o inner + i at o N inner + n inner + i
+  for (int64_t e = threadIdx.x; e < (int64_t)nl * N; e += kNatThreads) {
+    int b, n;
+    if (inner >= B) {
+      b = (int)(e % nl);
+      n = (int)(e / nl);
+    } else {
+      b = (int)(e / N);
+      n = (int)(e % N);
+    }
+    int64_t L = line0 + b;
+    int64_t o = L / inner, i = L % inner;
+    lds[(int64_t)b * N + n] = in[o * N * inner + (int64_t)n * inner + i];
+  }
+  __syncthreads();
+  int Ns = 1;
+  for (int p = 0; p < A.npass; p++) {
+    int R = A.radix[p];
+    if (R == 8) stockham_pass<8, DIR>(lds, nl, N, Ns, A.tw);
+    else if (R == 4) stockham_pass<4, DIR>(lds, nl, N, Ns, A.tw);
+    else if (R == 3) stockham_pass<3, DIR>(lds, nl, N, Ns, A.tw);
+    else stockham_pass<2, DIR>(lds, nl, N, Ns, A.tw);
+    Ns *= R;
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)nl * N; e += kNatThreads) {
+    int b, n;
+    if (inner >= B) {
+      b = (int)(e % nl);
+      n = (int)(e / nl);
+    } else {
+      b = (int)(e / N);
+      n = (int)(e % N);
+    }
+    int64_t L = line0 + b;
+    int64_t o = L / inner, i = L % inner;
+    double2 v = lds[(int64_t)b * N + n];
+    if (post_scale != 1.0) v = make_double2(v.x * post_scale, v.y * post_scale);
+    out[o * N * inner + (int64_t)n * inner + i] = v;
+  }
+}
+
+__global__ void scale_kernel(void* data, int64_t n, double f, int tgt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (tgt == 0) ((double*)data)[i] *= f;
+  else ((float*)data)[i] = (float)((double)((float*)data)[i] * f);
+}
+
+hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n_scalars + 255) / 256)), dim3(256), 0, st, data, n_scalars,
+                     factor, tgt);
+  return hipGetLastError();
+}
+
+static bool factor_radices(int64_t N, NatAxis& A) {
+  int np = 0;
+  int64_t m = N;
+  while (m > 1) {
+    int r;
+    if (m % 8 == 0) r = 8;
+    else if (m % 4 == 0) r = 4;
+    else if (m % 2 == 0) r = 2;
+    else if (m % 3 == 0) r = 3;
+    else return false;
+    if (np >= kMaxPasses) return false;
+    A.radix[np++] = r;
+    m /= r;
+  }
+  A.npass = np;
+  return true;
+}
+
+void native_plan_destroy(NativePlan* np);
+
+NativePlan* native_plan_create(const int64_t* n, std::string& err) {
+  NativePlan* np = new NativePlan();
+  for (int a = 0; a < 3; a++) {
+    np->n[a] = n[a];
+    NatAxis& A = np->ax[a];
+    A.N = n[a];
+    A.inner = 1;
+    A.outer = 1;
+    for (int b = a + 1; b < 3; b++) A.inner *= n[b];
+    for (int b = 0; b < a; b++) A.outer *= n[b];
+    if (A.N > kNatLdsComplex || !factor_radices(A.N, A)) {
+      err = "unsupported native length";
+      delete np;
+      return nullptr;
+    }
+    int64_t B = kNatLdsComplex / A.N;
+    if (B > 64) B = 64;
+    for (int p = 0; p < A.npass; p++) {
+      int64_t cap = (int64_t)kNatThreads * (kNatRegs / A.radix[p]) * A.radix[p] / A.N;
+      if (B > cap) B = cap;
+    }
+    if (B < 1) {
+      err = "native length too long";
+      delete np;
+      return nullptr;
+    }
+    A.B = (int)B;
+    // twiddles: nearest doubles of (cos, -sin)(2 pi t / N), from a 2^62-scaled
+    // double-double evaluation rounded to 53 bits
+    std::vector<int64_t> q;
+    quantised_roots(A.N, 61, q);
+    std::vector<double2> tw(A.N);
+    for (int64_t t = 0; t < A.N; t++) tw[t] = make_double2(std::ldexp((double)q[2 * t], -61),
+                                                          std::ldexp((double)q[2 * t + 1], -61));
+    void* d = nullptr;
+    if (hipMalloc(&d, A.N * sizeof(double2)) != hipSuccess ||
+        hipMemcpy(d, tw.data(), A.N * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+      err = "twiddle upload failed";
+      native_plan_destroy(np);
+      return nullptr;
+    }
+    np->allocs.push_back(d);
+    A.tw = (const double2*)d;
+  }
+  return np;
+}
+
+void native_plan_destroy(NativePlan* np) {
+  if (!np) return;
+  for (void* d : np->allocs) hipFree(d);
+  delete np;
+}
+
+hipError_t native_execute(NativePlan* np, const void* in, void* out, void* /*ws*/, int inverse, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)native_axis_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        kNatLdsComplex * 16);
+    hipFuncSetAttribute((const void*)native_axis_kernel<-1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        kNatLdsComplex * 16);
+    attr = true;
+  }
+  int64_t total = np->n[0] * np->n[1] * np->n[2];
+  const double2* src = (const double2*)in;
+  for (int k = 0; k < 3; k++) {
+    int a = 2 - k;
+    NatAxis A = np->ax[a];
+    int64_t nlines = A.outer * A.inner;
+    int64_t grid = (nlines + A.B - 1) / A.B;
+    size_t lds = (size_t)A.B * A.N * sizeof(double2);
+    double ps = (inverse && k == 2) ? 1.0 / (double)total : 1.0;
+    if (inverse)
+      hipLaunchKernelGGL(native_axis_kernel<-1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
+                         (double2*)out, A, ps);
+    else
+      hipLaunchKernelGGL(native_axis_kernel<1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
+                         (double2*)out, A, ps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = (const double2*)out;
+  }
+  return hipSuccess;
+}
+
+}  // namespace obfft

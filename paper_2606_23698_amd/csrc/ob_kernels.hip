@@ -1,0 +1,524 @@
+// Ozaki-Bailey stage kernels for gfx950 (MI355X).
+//
+// One launch computes one Bailey stage of one axis for every line of the
+// array (Alg. 1): per contraction column it extracts the shared power-of-two
+// scale, quantises Re and Im to k-bit integers, reduces them modulo every
+// m_i (Sec. 2, Eq. ozaki), runs the three Karatsuba real GEMMs per modulus on
+// MFMA (Sec. 2; Sec. 4.1 Eq. wmma), combines R = D - E and I = F - D - E in
+// the residue domain and canonicalises them (Alg. 1), and reconstructs each
+// output exactly by the Phase-A FP16 MFMA GEMM (Sec. 4.2) and the Kulisch
+// Phase B with the two-sided lift and a correctly rounded pack (Sec. 5.1,
+// Alg. 2).  The only FP64 arithmetic is the exponent/scale extraction and
+// quantisation at the start and the single rounding at the end.
+//
+// Work decomposition: a workgroup of 4 waves owns 64 contraction columns.
+// All columns of a workgroup share one stage matrix (stage 2: the same k2, so
+// the same twiddle-fused F_p^(k2), Sec. 4.1).  Per modulus:
+//   decon   every thread reduces K/4 elements of one column and writes their
+//           digit planes to LDS in the MFMA B-operand layout;
+//   GEMM    each wave multiplies its 16-row M-tile of the matrix planes (held
+//           in registers) with 16-column N-tiles from LDS;
+//   combine canonical residues of R and I go to an LDS array [output][m_i].
+// After the last modulus every wave runs Phase A on batches of 64 scalar
+// outputs (two 32x32x16 FP16 MFMAs plus one cross-half lane swap) and the
+// integer epilogue, one output per lane, and stores coalesced FP64 results.
+#include "ob_device.h"
+
+namespace obfft {
+
+template <int TGT>
+struct Tgt;
+template <>
+struct Tgt<0> {
+  typedef double T;
+  typedef double2 T2;
+  static constexpr int PREC = 53, R = 12, S = 15, TZ = 6, NW = 4;
+};
+template <>
+struct Tgt<1> {
+  typedef float T;
+  typedef float2 T2;
+  static constexpr int PREC = 24, R = 6, S = 8, TZ = 6, NW = 3;
+};
+
+template <int SUB>
+struct SubLayout;
+template <>
+struct SubLayout<SUB_FP8> {
+  static constexpr int BPL = 8;       // operand bytes per lane per MFMA
+  static constexpr int SLOTS = 32;    // K slots per MFMA
+  static constexpr int FMAX = 3;
+};
+template <>
+struct SubLayout<SUB_INT8> {
+  static constexpr int BPL = 16;
+  static constexpr int SLOTS = 64;
+  static constexpr int FMAX = 2;
+};
+
+__host__ __device__ constexpr int chunks_for(int sub, int K) {
+  return sub == SUB_INT8 ? (2 * K + 63) / 64 : (4 * K + 31) / 32;
+}
+
+__host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
+
+// LDS bytes of one digit buffer.
+__host__ __device__ constexpr int dig_bytes(int sub, int kmax) {
+  return 3 * chunks_for(sub, kmax) * kNT * 64 * (sub == SUB_INT8 ? 16 : 8);
+}
+
+inline int stage_lds_bytes(int sub, int kq, int K, int R) {
+  int dig = dig_bytes(sub, 4 * kq);
+  int res = align16(kCols * K * 2 * R * 2);
+  return 2 * dig + res + 64 * 8 * 2 + 64 * 4 + 256 * 4;
+}
+
+// Writes the digit planes of one residue v (centred, exact integer in FP32)
+// of column jc, contraction index s, Karatsuba form `form` (0: a~, 1: b~,
+// 2: a~ + b~) into the B-operand layout.
+template <int SUB, int CHB>
+__device__ __forceinline__ void put_digits(unsigned char* dig, int form, int jc, int s, float v,
+                                           int nd) {
+  if (SUB == SUB_FP8) {
+    if (nd == 3) {
+      // balanced radix-32 digits, |d| <= 16, exact in E4M3
+      float t1 = __builtin_rintf(v * 0.03125f);
+      float d0 = __builtin_fmaf(-32.0f, t1, v);
+      float t2 = __builtin_rintf(t1 * 0.03125f);
+      float d1 = __builtin_fmaf(-32.0f, t2, t1);
+      uint32_t wd = fp8_pack2<false>(d0, d1, 0u);
+      wd = fp8_pack2<true>(t2, 0.0f, wd);
+      int slot = s * 4, ch = slot >> 5, kk = slot & 31;
+      int ln = (jc & 15) + 16 * (kk >> 3);
+      int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
+      *(uint32_t*)(dig + off) = wd;
+    } else {
+      float t1 = __builtin_rintf(v * 0.03125f);
+      float d0 = __builtin_fmaf(-32.0f, t1, v);
+      uint32_t wd = fp8_pack2<false>(d0, t1, 0u);
+      int slot = s * 2, ch = slot >> 5, kk = slot & 31;
+      int ln = (jc & 15) + 16 * (kk >> 3);
+      int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
+      *(uint16_t*)(dig + off) = (uint16_t)wd;
+    }
+  } else {
+    // two signed 8-bit limbs, v = d0 + 128 d1, |d0| <= 64, |d1| <= 8
+    float t1 = __builtin_rintf(v * 0.0078125f);
+    float d0 = __builtin_fmaf(-128.0f, t1, v);
+    uint32_t wd = ((uint32_t)(int)d0 & 0xFFu) | (((uint32_t)(int)t1 & 0xFFu) << 8);
+    int slot = s * 2, ch = slot >> 6, kk = slot & 63;
+    int ln = (jc & 15) + 16 * (kk >> 4);
+    int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 16 + (kk & 15);
+    *(uint16_t*)(dig + off) = (uint16_t)wd;
+  }
+}
+
+// Phase A + Phase B for 64 scalar outputs held as canonical residues in LDS
+// or global memory; returns the partials after the lane-half swap.
+template <int NV>
+__device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, float* yv) {
+  v16f c;
+#pragma unroll
+  for (int v = 0; v < 16; v++) c[v] = 8388608.0f;  // 2^23: the deposit bias
+  v16f d1 = mfma_f16_32(aop, b1, c);
+  v16f d2 = mfma_f16_32(aop, b2, c);
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    auto pr = __builtin_amdgcn_permlane32_swap(__float_as_uint(d1[v]), __float_as_uint(d2[v]),
+                                               false, false);
+    xv[v] = __uint_as_float(pr[0]);
+    yv[v] = __uint_as_float(pr[1]);
+  }
+}
+
+template <int SUB, int TGT, int KQ>
+__global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
+                                                            const CrtConsts C) {
+  typedef Tgt<TGT> TT;
+  typedef SubLayout<SUB> SL;
+  constexpr int R = TT::R;
+  constexpr int KMAX = 4 * KQ;
+  constexpr int MT = (KMAX + 15) / 16;
+  constexpr int NTW = kNT * MT / 4;
+  constexpr int CHB = chunks_for(SUB, KMAX);
+  constexpr int DIG = dig_bytes(SUB, KMAX);
+  typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = P.K;
+  unsigned char* dig0 = smem;
+  unsigned char* dig1 = smem + DIG;
+  const int res_bytes = align16(kCols * K * 2 * R * 2);
+  uint16_t* res = (uint16_t*)(smem + 2 * DIG);
+  int64_t* col_in = (int64_t*)(smem + 2 * DIG + res_bytes);
+  int64_t* col_out = col_in + 64;
+  int* cexp = (int*)(col_out + 64);
+  int* pexp = cexp + 64;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t g = 0, cstart;
+  if (P.stage == 1) {
+    cstart = (int64_t)blockIdx.x * kCols;
+  } else {
+    g = blockIdx.x / P.tiles_per_g;
+    cstart = (int64_t)(blockIdx.x % P.tiles_per_g) * kCols;
+  }
+  if (tid < 64) {
+    int64_t c = cstart + tid;
+    int64_t ci = -1, co = -1;
+    if (c < P.ncols) {
+      int64_t i = c % P.inner, rest = c / P.inner, o, gg;
+      if (P.stage == 1) {
+        gg = rest % P.G;
+        o = rest / P.G;
+      } else {
+        gg = g;
+        o = rest;
+      }
+      ci = o * P.s_o + gg * P.s_in_g + i;
+      co = o * P.s_o + gg * P.s_out_g + i;
+    }
+    col_in[tid] = ci;
+    col_out[tid] = co;
+  }
+  for (int x = tid * 16; x < 2 * DIG; x += kThreads * 16) *(uint4*)(smem + x) = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+
+  // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
+  const int jc = tid & 63, part = tid >> 6;
+  const int64_t cin = col_in[jc];
+  double ar[KQ], br[KQ];
+  int lmax = INT_MIN;
+#pragma unroll
+  for (int u = 0; u < KQ; u++) {
+    int s = part * KQ + u;
+    double xr = 0.0, xi = 0.0;
+    if (cin >= 0 && s < K) {
+      typename TT::T2 v = ((const typename TT::T2*)P.in)[cin + (int64_t)s * P.s_in_s];
+      xr = (double)v.x;
+      xi = (double)v.y;
+    }
+    if (xr != 0.0) lmax = max(lmax, __builtin_amdgcn_frexp_exp(xr) - 1);
+    if (xi != 0.0) lmax = max(lmax, __builtin_amdgcn_frexp_exp(xi) - 1);
+    ar[u] = xr;
+    br[u] = xi;
+  }
+  pexp[part * 64 + jc] = lmax;
+  __syncthreads();
+  int e = max(max(pexp[jc], pexp[64 + jc]), max(pexp[128 + jc], pexp[192 + jc]));
+  if (e == INT_MIN) e = 0;  // all-zero column: every output is zero
+  if (part == 0) cexp[jc] = e;
+#pragma unroll
+  for (int u = 0; u < KQ; u++) {
+    ar[u] = __builtin_rint(__builtin_ldexp(ar[u], TT::PREC - 1 - e));
+    br[u] = __builtin_rint(__builtin_ldexp(br[u], TT::PREC - 1 - e));
+  }
+
+  const int mt = (MT == 2) ? (wave & 1) : 0;
+  const uint8_t* amat = P.amat + g * P.amat_g_stride;
+
+  for (int i = 0; i < R; i++) {
+    unsigned char* dig = (i & 1) ? dig1 : dig0;
+    const double md = (double)MC.m[i], imd = MC.inv_md[i];
+    const float mf = (float)MC.m[i], imf = MC.inv_mf[i];
+    const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
+    // ---- deconstruction: residues and digit planes (Sec. 2, Eq. ozaki) ----
+#pragma unroll
+    for (int u = 0; u < KQ; u++) {
+      int s = part * KQ + u;
+      if (s < K) {
+        float ra = residue_f64(ar[u], md, imd);
+        float rb = residue_f64(br[u], md, imd);
+        float rs = reduce_f32(ra + rb, mf, imf);
+        put_digits<SUB, CHB>(dig, 0, jc, s, ra, nd);
+        put_digits<SUB, CHB>(dig, 1, jc, s, rb, nd);
+        put_digits<SUB, CHB>(dig, 2, jc, s, rs, nd);
+      }
+    }
+    __syncthreads();
+    // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) and the combines ----
+    const uint8_t* amod = amat + i * P.amat_mod_stride;
+#pragma unroll
+    for (int w = 0; w < NTW; w++) {
+      const int nt = (MT == 2) ? ((wave >> 1) + 2 * w) : wave;
+      float Dv[4], Ev[4], Fv[4];
+      if (SUB == SUB_FP8) {
+        const int ndp = nd == 3 ? 4 : 2;
+        const int nch = (ndp * K + 31) >> 5;
+        v4f acc[3][3];
+#pragma unroll
+        for (int f = 0; f < 3; f++)
+#pragma unroll
+          for (int fo = 0; fo < 3; fo++) acc[f][fo] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int form = 0; form < 3; form++) {
+          for (int ch = 0; ch < nch; ch++) {
+            long bop = *(const long*)(dig + (((form * CHB + ch) * kNT + nt) * 64 + lane) * 8);
+#pragma unroll
+            for (int f = 0; f < 3; f++) {
+              if (f < nd) {
+                const uint8_t* ap =
+                    amod + ((((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) * P.amat_chmax + ch) * 512 +
+                    lane * 8;
+                long aop = *(const long*)ap;
+                acc[form][f] = mfma_fp8(aop, bop, acc[form][f]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          Dv[v] = __builtin_fmaf(1024.0f, acc[0][2][v], __builtin_fmaf(32.0f, acc[0][1][v], acc[0][0][v]));
+          Ev[v] = __builtin_fmaf(1024.0f, acc[1][2][v], __builtin_fmaf(32.0f, acc[1][1][v], acc[1][0][v]));
+          Fv[v] = __builtin_fmaf(1024.0f, acc[2][2][v], __builtin_fmaf(32.0f, acc[2][1][v], acc[2][0][v]));
+        }
+      } else {
+        v4i acc[3][2];
+#pragma unroll
+        for (int f = 0; f < 3; f++)
+#pragma unroll
+          for (int fo = 0; fo < 2; fo++) acc[f][fo] = (v4i){0, 0, 0, 0};
+        const int nch = (2 * K + 63) >> 6;
+#pragma unroll
+        for (int form = 0; form < 3; form++) {
+          for (int ch = 0; ch < nch; ch++) {
+            v4i bop = *(const v4i*)(dig + (((form * CHB + ch) * kNT + nt) * 64 + lane) * 16);
+#pragma unroll
+            for (int f = 0; f < 2; f++) {
+              const uint8_t* ap =
+                  amod + ((((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) * P.amat_chmax + ch) * 1024 +
+                  lane * 16;
+              v4i aop = *(const v4i*)ap;
+              acc[form][f] = mfma_i8(aop, bop, acc[form][f]);
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          Dv[v] = (float)(acc[0][0][v] + (acc[0][1][v] << 7));
+          Ev[v] = (float)(acc[1][0][v] + (acc[1][1][v] << 7));
+          Fv[v] = (float)(acc[2][0][v] + (acc[2][1][v] << 7));
+        }
+      }
+      const int col = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = 16 * mt + 4 * (lane >> 4) + v;
+        if (row < K) {
+          float rr = canonical_f32(Dv[v] - Ev[v], mf, imf);
+          float ri = canonical_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+          int id = ((nt * K + row) * 16 + (lane & 15)) * 2;
+          res[id * R + i] = __builtin_bit_cast(uint16_t, (_Float16)rr);
+          res[(id + 1) * R + i] = __builtin_bit_cast(uint16_t, (_Float16)ri);
+          if (P.dbg_res) {
+            int64_t co = col_out[col];
+            if (co >= 0) {
+              int64_t el = co + (int64_t)row * P.s_out_t;
+              P.dbg_res[(el * 2) * R + i] = (uint16_t)rr;
+              P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)ri;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- Phase A (FP16 MFMA) + Phase B (Kulisch, lift, pack) ----
+  v8h aop = *(const v8h*)(P.phaseA + lane * 8);
+  const int h = lane >> 5;
+  const int nbatch = kNT * K / 2;
+  for (int b = wave; b < nbatch; b += 4) {
+    const int nt = b / (K / 2), rp = b % (K / 2);
+    const int id1 = (nt * K + 2 * rp) * 32 + (lane & 31);
+    v8h b1, b2;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      int k = 8 * h + j;
+      b1[j] = k < R ? __builtin_bit_cast(_Float16, res[id1 * R + k]) : (_Float16)0.0f;
+      b2[j] = k < R ? __builtin_bit_cast(_Float16, res[(id1 + 32) * R + k]) : (_Float16)0.0f;
+    }
+    float xv[EP::NV], yv[EP::NV];
+    phase_a<EP::NV>(aop, b1, b2, xv, yv);
+    uint32_t wv[(TT::S + 3) / 4 + 1];
+    EP::deposits(xv, yv, wv, &wv[(TT::S + 3) / 4]);
+    uint32_t zh = EP::zhat(xv, yv, C.Czh);
+    uint32_t Rw[TT::NW];
+    EP::lift(wv, zh, C, Rw);
+    const int row = 2 * rp + (lane >> 5);
+    const int col = nt * 16 + ((lane >> 1) & 15);
+    const int prt = lane & 1;
+    const int64_t co = col_out[col];
+    if (co >= 0 && row < K) {
+      const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
+      typename TT::T* o = (typename TT::T*)P.out;
+      int64_t idx = (co + (int64_t)row * P.s_out_t) * 2 + prt;
+      if (TGT == 0)
+        o[idx] = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
+      else
+        o[idx] = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
+    }
+  }
+}
+
+// ---- standalone CRT reconstruction (unit-level access to Phase A / B) ----
+template <int TGT>
+__global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* residues, const int* exps,
+                                                  void* out, uint32_t* taps, const uint16_t* phaseA,
+                                                  const CrtConsts C) {
+  typedef Tgt<TGT> TT;
+  constexpr int R = TT::R;
+  typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  if (base >= n) return;
+  const int h = lane >> 5;
+  v8h aop = *(const v8h*)(phaseA + lane * 8);
+  v8h b1, b2;
+  const int64_t o1 = base + (lane & 31), o2 = o1 + 32;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    int k = 8 * h + j;
+    b1[j] = (k < R && o1 < n) ? (_Float16)(float)residues[o1 * R + k] : (_Float16)0.0f;
+    b2[j] = (k < R && o2 < n) ? (_Float16)(float)residues[o2 * R + k] : (_Float16)0.0f;
+  }
+  float xv[EP::NV], yv[EP::NV];
+  phase_a<EP::NV>(aop, b1, b2, xv, yv);
+  constexpr int NC = (TT::S + 3) / 4;
+  uint32_t wv[NC + 1];
+  EP::deposits(xv, yv, wv, &wv[NC]);
+  uint32_t zh = EP::zhat(xv, yv, C.Czh);
+  uint32_t Rw[TT::NW];
+  EP::lift(wv, zh, C, Rw);
+  const int64_t o = base + lane;
+  if (o < n) {
+    const int ex = exps[o];
+    if (TGT == 0)
+      ((double*)out)[o] = pack_f64<TT::NW>(Rw, ex);
+    else
+      ((float*)out)[o] = pack_f32<TT::NW>(Rw, ex);
+    if (taps) {
+      uint32_t* tp = taps + o * kTapStride;
+      for (int s = 0; s < TT::S; s++) tp[s] = EP::pbits(xv, yv, s) - 0x4B000000u;
+      for (int t = 0; t < TT::TZ; t++) tp[16 + t] = EP::zbits(xv, yv, t) - 0x4B000000u;
+      // E = E_b - Bp (mod 2^160)
+      uint32_t E[5], bw = 0;
+      for (int i = 0; i < 5; i++) {
+        uint32_t wi = i <= NC ? wv[i] : 0u;
+        E[i] = subc(wi, C.Bp5[i], bw, &bw);
+      }
+      for (int i = 0; i < 5; i++) tp[24 + i] = E[i];
+      tp[29] = zh;
+      for (int i = 0; i < 4; i++) tp[30 + i] = i < TT::NW ? Rw[i] : (uint32_t)((int32_t)Rw[TT::NW - 1] >> 31);
+      tp[34] = (uint32_t)ex;
+    }
+  }
+}
+
+// ---- plan-time conversion of signed digit planes to E4M3 ----
+__global__ void digits_to_fp8_kernel(uint8_t* p, int64_t n4) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  uint32_t w = ((const uint32_t*)p)[i];
+  float d0 = (float)(int8_t)(w & 0xFF), d1 = (float)(int8_t)((w >> 8) & 0xFF);
+  float d2 = (float)(int8_t)((w >> 16) & 0xFF), d3 = (float)(int8_t)(w >> 24);
+  uint32_t o = fp8_pack2<false>(d0, d1, 0u);
+  o = fp8_pack2<true>(d2, d3, o);
+  ((uint32_t*)p)[i] = o;
+}
+
+// ---- MFMA contract probes (layout and exact integer accumulation) ----
+__global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* d) {
+  const int lane = threadIdx.x;
+  if (kind == 0) {
+    long av = ((const long*)a)[lane], bv = ((const long*)b)[lane];
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    ((v4f*)d)[lane] = mfma_fp8(av, bv, c);
+  } else if (kind == 1) {
+    v4i av = ((const v4i*)a)[lane], bv = ((const v4i*)b)[lane];
+    v4i c = {0, 0, 0, 0};
+    ((v4i*)d)[lane] = mfma_i8(av, bv, c);
+  } else if (kind == 2) {
+    v8h av = ((const v8h*)a)[lane], bv = ((const v8h*)b)[lane];
+    v16f c;
+    for (int v = 0; v < 16; v++) c[v] = 0.f;
+    ((v16f*)d)[lane] = mfma_f16_32(av, bv, c);
+  } else if (kind == 3) {
+    uint32_t x = ((const uint32_t*)a)[lane], y = ((const uint32_t*)b)[lane];
+    auto pr = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    ((uint32_t*)d)[lane] = pr[0];
+    ((uint32_t*)d)[64 + lane] = pr[1];
+  } else if (kind == 4) {
+    // E4M3 conversion of small integers: a = 64 floats, d = 64 bytes
+    float x = ((const float*)a)[lane];
+    uint32_t w = fp8_pack2<false>(x, 0.0f, 0u);
+    ((uint8_t*)d)[lane] = (uint8_t)(w & 0xFF);
+  }
+}
+
+// ---- host-side launch helpers ----
+template <int SUB, int TGT, int KQ>
+static hipError_t launch_stage_t(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
+                                 int64_t grid, hipStream_t st) {
+  int lds = stage_lds_bytes(SUB, KQ, P.K, Tgt<TGT>::R);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KQ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KQ>), dim3((unsigned)grid), dim3(kThreads), lds, st, P,
+                     MC, C);
+  return hipGetLastError();
+}
+
+template <int SUB, int TGT>
+static hipError_t launch_stage_k(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
+                                 int64_t grid, hipStream_t st) {
+  int K = P.K;
+  if (K <= 4) return launch_stage_t<SUB, TGT, 1>(P, MC, C, grid, st);
+  if (K <= 8) return launch_stage_t<SUB, TGT, 2>(P, MC, C, grid, st);
+  if (K <= 12) return launch_stage_t<SUB, TGT, 3>(P, MC, C, grid, st);
+  if (K <= 16) return launch_stage_t<SUB, TGT, 4>(P, MC, C, grid, st);
+  return launch_stage_t<SUB, TGT, 8>(P, MC, C, grid, st);
+}
+
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
+                        int64_t grid, hipStream_t st) {
+  if (sub == SUB_INT8)
+    return tgt == 0 ? launch_stage_k<SUB_INT8, 0>(P, MC, C, grid, st)
+                    : launch_stage_k<SUB_INT8, 1>(P, MC, C, grid, st);
+  return tgt == 0 ? launch_stage_k<SUB_FP8, 0>(P, MC, C, grid, st)
+                  : launch_stage_k<SUB_FP8, 1>(P, MC, C, grid, st);
+}
+
+int stage_lds_bytes_for(int sub, int K, int tgt) {
+  int kq = K <= 4 ? 1 : K <= 8 ? 2 : K <= 12 ? 3 : K <= 16 ? 4 : 8;
+  return stage_lds_bytes(sub, kq, K, tgt == 0 ? 12 : 6);
+}
+
+hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
+                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts& C, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (tgt == 0)
+    hipLaunchKernelGGL(crt_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, n, residues, exps, out, taps,
+                       phaseA, C);
+  else
+    hipLaunchKernelGGL(crt_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, n, residues, exps, out, taps,
+                       phaseA, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st) {
+  int64_t n4 = bytes / 4;
+  hipLaunchKernelGGL(digits_to_fp8_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, p, n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st) {
+  hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, st, kind, a, b, d);
+  return hipGetLastError();
+}
+
+}  // namespace obfft

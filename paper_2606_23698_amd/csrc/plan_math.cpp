@@ -1,0 +1,376 @@
+// Plan-time mathematics of the Ozaki-Bailey FFT (host only).
+//
+//  * modulus set, M, CRT idempotents u_k, byte slices, lift weights w_k
+//    (Sec. 2, Eq. capacity; Sec. 4.2, Eqs. fcrt and slicing; Sec. 5.1);
+//  * quantised roots of unity Q(w_N^t) = RNE(2^B (cos, -sin)(2 pi t / N)),
+//    evaluated in double-double arithmetic (Sec. 4.1, Eq. twiddle-fusion:
+//    the fused coefficient is one quantised root);
+//  * the MFMA operand planes of the residue GEMMs and of the Phase-A GEMM.
+#include "plan_math.h"
+
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace obfft {
+
+static int bitlen(u128 x) {
+  int n = 0;
+  while (x) { n++; x >>= 1; }
+  return n;
+}
+
+static int64_t modinv(int64_t a, int64_t m) {
+  int64_t t = 0, nt = 1, r = m, nr = ((a % m) + m) % m;
+  while (nr) {
+    int64_t qq = r / nr;
+    int64_t tmp = t - qq * nt; t = nt; nt = tmp;
+    tmp = r - qq * nr; r = nr; nr = tmp;
+  }
+  if (r != 1) return -1;
+  return t < 0 ? t + m : t;
+}
+
+static int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+bool build_modset(const int32_t* mods, int r, ModSet& H, std::string& err) {
+  if (r < 2 || r > kMaxModuli) { err = "modulus count out of range"; return false; }
+  H.r = r;
+  H.M = 1;
+  H.log2M = 0.0;
+  for (int k = 0; k < r; k++) {
+    if (mods[k] < 2 || mods[k] >= 2048) { err = "modulus out of range [2, 2048)"; return false; }
+    for (int j = 0; j < k; j++)
+      if (gcd64(mods[j], mods[k]) != 1) { err = "moduli not pairwise coprime"; return false; }
+    H.m[k] = mods[k];
+    H.M *= (u128)mods[k];
+    H.log2M += std::log2((double)mods[k]);
+  }
+  if (bitlen(H.M) > 124) { err = "modulus product too large"; return false; }
+  for (int k = 0; k < r; k++) {
+    u128 Mk = H.M / (u128)H.m[k];
+    int64_t inv = modinv((int64_t)(Mk % (u128)H.m[k]), H.m[k]);
+    H.u[k] = Mk * (u128)inv;   // < M since inv < m_k
+  }
+  H.S = (bitlen(H.M) + 7) / 8;
+  // w_k = round(2^48 u_k / M): 48 steps of binary long division of u_k / M.
+  H.T = 0;
+  for (int k = 0; k < r; k++) {
+    u128 rem = H.u[k];
+    uint64_t qv = 0;
+    for (int i = 0; i < kFracBits; i++) {
+      rem <<= 1;
+      qv <<= 1;
+      if (rem >= H.M) { rem -= H.M; qv |= 1; }
+    }
+    if (2 * rem == H.M) { err = "tie in lift weight"; return false; }
+    if (2 * rem > H.M) qv++;
+    H.w[k] = qv;
+    int nb = 0;
+    for (uint64_t x = qv; x; x >>= 8) nb++;
+    if (nb > H.T) H.T = nb;
+  }
+  return true;
+}
+
+double capacity_bits(int64_t Kmax, int kbits) {
+  return 1.0 + std::log2((double)Kmax) + 2.0 * (kbits + 1);
+}
+
+// ---- 160-bit helpers (little-endian 32-bit words) ----
+static void add_shifted(uint32_t* acc, int nw, uint64_t v, int bitpos) {
+  // acc += v << bitpos (mod 2^(32 nw))
+  int w = bitpos / 32, o = bitpos % 32;
+  u128 x = (u128)v << o;
+  uint64_t carry = 0;
+  for (int i = w; i < nw; i++) {
+    uint64_t s = (uint64_t)acc[i] + (uint64_t)(uint32_t)x + carry;
+    acc[i] = (uint32_t)s;
+    carry = s >> 32;
+    x >>= 32;
+  }
+}
+
+static void sub_words(uint32_t* a, const uint32_t* b, int nw) {
+  int64_t borrow = 0;
+  for (int i = 0; i < nw; i++) {
+    int64_t d = (int64_t)a[i] - (int64_t)b[i] - borrow;
+    borrow = d < 0;
+    a[i] = (uint32_t)d;
+  }
+}
+
+void build_crt_consts(const ModSet& H, CrtConsts& C) {
+  memset(&C, 0, sizeof(C));
+  C.r = H.r;
+  C.S = H.S;
+  C.T = H.T;
+  C.nwords = (bitlen(H.M) + 2 <= 96) ? 3 : 4;
+  u128 M = H.M, Mh = H.M >> 1;
+  for (int i = 0; i < 4; i++) {
+    C.M[i] = (uint32_t)(M >> (32 * i));
+    C.Mhalf[i] = (uint32_t)(Mh >> (32 * i));
+  }
+  // Each Phase-A partial leaves the MFMA as an FP32 value 2^23 + P (the
+  // accumulator starts at 2^23), whose bit pattern is 0x4B000000 + P.  The
+  // deposits therefore carry an implicit bias Bp = sum_s 0x4B000000 256^s.
+  uint32_t Bp[5] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < H.S; s++) add_shifted(Bp, 5, kFloatBiasBits, 8 * s);
+  memcpy(C.Bp5, Bp, sizeof(Bp));
+  uint32_t K0[5] = {C.Mhalf[0], C.Mhalf[1], C.Mhalf[2], C.Mhalf[3], 0};
+  sub_words(K0, Bp, 5);
+  for (int i = 0; i < 4; i++) C.K0[i] = K0[i];
+  uint64_t Bz = 0;
+  for (int t = 0; t < H.T; t++) Bz += (uint64_t)kFloatBiasBits << (8 * t);
+  C.Czh = ((uint64_t)1 << (kFracBits - 1)) - Bz;
+}
+
+// ---- double-double trigonometry ----
+namespace {
+struct DD {
+  double hi, lo;
+};
+inline DD two_sum(double a, double b) {
+  double s = a + b, v = s - a;
+  return {s, (a - (s - v)) + (b - v)};
+}
+inline DD fast_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+inline DD operator+(DD a, DD b) {
+  DD s = two_sum(a.hi, b.hi), t = two_sum(a.lo, b.lo);
+  double lo = s.lo + t.hi;
+  DD u = fast_two_sum(s.hi, lo);
+  lo = u.lo + t.lo;
+  return fast_two_sum(u.hi, lo);
+}
+inline DD operator-(DD a) { return {-a.hi, -a.lo}; }
+inline DD operator-(DD a, DD b) { return a + (-b); }
+inline DD operator*(DD a, DD b) {
+  double p = a.hi * b.hi;
+  double e = std::fma(a.hi, b.hi, -p);
+  e += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p, e);
+}
+inline DD div_int(DD a, double d) {
+  // (a / d) to double-double accuracy, d a small exact integer
+  double q1 = a.hi / d;
+  double p = q1 * d;
+  double pe = std::fma(q1, d, -p);
+  DD rem = (a - DD{p, pe});
+  double q2 = rem.hi / d;
+  return fast_two_sum(q1, q2);
+}
+const DD kHalfPi = {1.5707963267948966, 6.123233995736766e-17};
+
+// sin and cos of x in [0, pi/4] by Taylor series in double-double.
+void sincos_small(DD x, DD& s, DD& c) {
+  DD x2 = x * x;
+  DD term = x;
+  s = x;
+  for (int n = 1; n < 16; n++) {
+    term = div_int(term * x2, (double)((2 * n) * (2 * n + 1)));
+    s = (n & 1) ? s - term : s + term;
+  }
+  term = {1.0, 0.0};
+  c = term;
+  for (int n = 1; n < 16; n++) {
+    term = div_int(term * x2, (double)((2 * n - 1) * (2 * n)));
+    c = (n & 1) ? c - term : c + term;
+  }
+}
+
+int64_t rne_dd(DD v) {
+  double n = std::nearbyint(v.hi);
+  double frac = (v.hi - n) + v.lo;
+  if (frac > 0.5) return (int64_t)n + 1;
+  if (frac < -0.5) return (int64_t)n - 1;
+  if (frac == 0.5 || frac == -0.5) {
+    int64_t a = (int64_t)n, b = frac > 0 ? a + 1 : a - 1;
+    return (a % 2 == 0) ? a : b;
+  }
+  return (int64_t)n;
+}
+}  // namespace
+
+void quantised_roots(int64_t N, int bits, std::vector<int64_t>& out) {
+  out.assign(2 * N, 0);
+  double scale = std::ldexp(1.0, bits);
+  for (int64_t t = 0; t < N; t++) {
+    // angle 2 pi t / N = (pi/2) (Q + f), Q = floor(4t/N), f = (4t - QN)/N
+    int64_t q4 = 4 * t;
+    int64_t Q = q4 / N;
+    int64_t r4 = q4 - Q * N;
+    bool flip = 2 * r4 > N;        // use the complementary angle for f > 1/2
+    int64_t num = flip ? N - r4 : r4;
+    double fh = (double)num / (double)N;
+    double fl = std::fma(-fh, (double)N, (double)num) / (double)N;
+    DD psi = kHalfPi * DD{fh, fl};
+    DD s, c;
+    sincos_small(psi, s, c);
+    if (flip) { DD tmp = s; s = c; c = tmp; }
+    DD cs, sn;   // cos and sin of the full angle
+    switch (Q & 3) {
+      case 0: cs = c; sn = s; break;
+      case 1: cs = -s; sn = c; break;
+      case 2: cs = -c; sn = -s; break;
+      default: cs = s; sn = -c; break;
+    }
+    DD a = cs * DD{scale, 0.0};
+    DD b = (-sn) * DD{scale, 0.0};
+    out[2 * t] = rne_dd(a);
+    out[2 * t + 1] = rne_dd(b);
+  }
+}
+
+// ---- MFMA operand planes ----
+
+static int centred(int64_t v, int m) {
+  int64_t r = v % m;
+  if (r < 0) r += m;
+  if (r > m / 2) r -= m;
+  return (int)r;
+}
+
+static int rne_div(int c, int R) {
+  // nearest integer to c / R, ties to even
+  double x = (double)c / (double)R;
+  return (int)std::nearbyint(x);
+}
+
+int fp8_digits(int m) { return m <= kFp8TwoDigitMax ? 2 : 3; }
+
+// Balanced radix-R digits of a centred residue (the same rule the kernels use
+// on the data side: d0 = v - R rne(v/R), then recurse on rne(v/R)).
+static void balanced_digits(int c, int R, int nd, int* d) {
+  for (int i = 0; i < nd - 1; i++) {
+    int q = rne_div(c, R);
+    d[i] = c - R * q;
+    c = q;
+  }
+  d[nd - 1] = c;
+}
+
+uint8_t e4m3_encode(int d) {
+  if (d == 0) return 0;
+  int sign = d < 0;
+  int a = sign ? -d : d;
+  int e = 31 - __builtin_clz((unsigned)a);
+  int mant = ((a << 3) >> e) - 8;
+  if ((((mant + 8) << e) >> 3) != a) throw std::runtime_error("digit not representable in E4M3");
+  return (uint8_t)((sign << 7) | ((e + 7) << 3) | mant);
+}
+
+uint16_t f16_encode_int(int v) {
+  if (v == 0) return 0;
+  int sign = v < 0;
+  int a = sign ? -v : v;
+  if (a > 2048) throw std::runtime_error("integer not FP16-exact");
+  int e = 31 - __builtin_clz((unsigned)a);
+  int mant = (a << 10 >> e) - 1024;
+  return (uint16_t)((sign << 15) | ((e + 15) << 10) | mant);
+}
+
+// Matrix entry (integer) of a stage: stage 1 F_q[t][s] = w_N^{p s t}; stage 2
+// F_p^(g)[t][s] = w_N^{s (g + q t)} -- one quantised root (Eq. twiddle-fusion).
+static void matrix_entry(const std::vector<int64_t>& roots, int64_t N, int64_t p, int64_t q,
+                         int stage, int64_t g, int64_t t, int64_t s, int direction,
+                         int64_t* c, int64_t* sn) {
+  int64_t idx = stage == 1 ? (p * s * t) % N : (s * (g + q * t)) % N;
+  *c = roots[2 * idx];
+  *sn = roots[2 * idx + 1] * (direction ? -1 : 1);
+}
+
+void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
+                          int64_t p, int64_t q, int stage, int direction, int substrate,
+                          std::vector<uint8_t>& bytes, OperandPlanes& L) {
+  int K = stage == 1 ? (int)q : (int)p;
+  int G = stage == 1 ? 1 : (int)q;
+  int MT = (K + 15) / 16;
+  int bpl, fmax, chmax;
+  if (substrate == SUB_INT8) { bpl = 16; fmax = 2; chmax = (2 * K + 63) / 64; }
+  else { bpl = 8; fmax = 3; chmax = (4 * K + 31) / 32; }
+  int64_t chunk_bytes = 64 * bpl;
+  L.fmax = fmax; L.chmax = chmax; L.mt = MT; L.G = G;
+  L.mod_stride = 3LL * fmax * MT * chmax * chunk_bytes;
+  L.g_stride = (int64_t)H.r * L.mod_stride;
+  bytes.assign((size_t)(L.g_stride * G), 0);
+  std::vector<int> cval(3 * K * K);
+  for (int g = 0; g < G; g++) {
+    for (int i = 0; i < H.r; i++) {
+      int m = H.m[i];
+      for (int t = 0; t < K; t++)
+        for (int s = 0; s < K; s++) {
+          int64_t c, sn;
+          matrix_entry(roots, N, p, q, stage, g, t, s, direction, &c, &sn);
+          cval[(0 * K + t) * K + s] = centred(c, m);
+          cval[(1 * K + t) * K + s] = centred(sn, m);
+          cval[(2 * K + t) * K + s] = centred(c + sn, m);
+        }
+      int R = substrate == SUB_INT8 ? 128 : 32;
+      int nd = substrate == SUB_INT8 ? 2 : fp8_digits(m);
+      int ndp = substrate == SUB_INT8 ? 2 : (nd == 3 ? 4 : 2);
+      int nf = nd;
+      int pw[3] = {1, R % m, (R * R) % m};
+      for (int form = 0; form < 3; form++)
+        for (int f = 0; f < fmax; f++)
+          for (int mt = 0; mt < MT; mt++)
+            for (int ch = 0; ch < chmax; ch++)
+              for (int lane = 0; lane < 64; lane++)
+                for (int j = 0; j < bpl; j++) {
+                  int t = 16 * mt + lane % 16;
+                  int kk = (substrate == SUB_INT8 ? 16 : 8) * (lane / 16) + j;
+                  int slot = (substrate == SUB_INT8 ? 64 : 32) * ch + kk;
+                  int s = slot / ndp, e = slot % ndp;
+                  int digit = 0;
+                  if (t < K && s < K && e < nd && f < nf) {
+                    int a = cval[(form * K + t) * K + s];
+                    int ce = centred((int64_t)a * pw[e], m);
+                    int d[3];
+                    balanced_digits(ce, R, nd, d);
+                    digit = d[f];
+                  }
+                  int64_t off = g * L.g_stride + i * L.mod_stride +
+                                ((((int64_t)form * fmax + f) * MT + mt) * chmax + ch) * chunk_bytes +
+                                lane * bpl + j;
+                  // FP8 planes hold the signed digit as int8 here; they are
+                  // converted to E4M3 on the device by the same instruction
+                  // the kernels use for the data digits.
+                  bytes[off] = (uint8_t)(int8_t)digit;
+                }
+    }
+  }
+}
+
+// Phase-A operand of v_mfma_f32_32x32x16_f16: A[row][k], row = partial
+// placement, k = modulus.  Lane l holds row l % 32, k = 8 (l / 32) + j.
+// Row rho is read back in register v = (rho % 4) + 4 (rho / 8) of lane half
+// (rho / 4) % 2; register pair v carries P_{2v}, P_{2v+1} for v < ceil(S/2)
+// and then the lift bytes Z_{2u}, Z_{2u+1}.
+void build_phaseA_operand(const ModSet& H, std::vector<uint16_t>& out, int* npairs) {
+  out.assign(64 * 8, 0);
+  int vp = (H.S + 1) / 2, vz = (H.T + 1) / 2;
+  *npairs = vp + vz;
+  for (int lane = 0; lane < 64; lane++)
+    for (int j = 0; j < 8; j++) {
+      int rho = lane % 32, k = 8 * (lane / 32) + j;
+      int v = (rho % 4) + 4 * (rho / 8), half = (rho / 4) % 2;
+      int val = 0;
+      if (k < H.r) {
+        if (v < vp) {
+          int s = 2 * v + half;
+          if (s < H.S) val = (int)((H.u[k] >> (8 * s)) & 0xFF);
+        } else if (v < vp + vz) {
+          int t = 2 * (v - vp) + half;
+          if (t < H.T) val = (int)((H.w[k] >> (8 * t)) & 0xFF);
+        }
+      }
+      out[lane * 8 + j] = f16_encode_int(val);
+    }
+}
+
+}  // namespace obfft

@@ -1,0 +1,41 @@
+// Plan-time mathematics (host only): modulus-set constants, quantised roots,
+// MFMA operand planes.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "obfft_internal.h"
+
+namespace obfft {
+
+typedef unsigned __int128 u128;
+
+constexpr int kFracBits = 48;                  // f of the fractional lift (Sec. 5.1)
+constexpr uint32_t kFloatBiasBits = 0x4B000000u; // bit pattern of 2^23 as FP32
+constexpr int kFp8TwoDigitMax = 1052;          // moduli up to here need 2 radix-32 digits
+
+struct ModSet {
+  int r;
+  int32_t m[kMaxModuli];
+  u128 M;
+  u128 u[kMaxModuli];     // CRT idempotents (Eq. fcrt)
+  uint64_t w[kMaxModuli]; // round(2^48 u_k / M) (Sec. 5.1)
+  int S, T;               // byte slices of u_k and w_k
+  double log2M;
+};
+
+bool build_modset(const int32_t* mods, int r, ModSet& H, std::string& err);
+double capacity_bits(int64_t Kmax, int kbits);
+void build_crt_consts(const ModSet& H, CrtConsts& C);
+void quantised_roots(int64_t N, int bits, std::vector<int64_t>& out);
+int fp8_digits(int m);
+uint8_t e4m3_encode(int d);
+uint16_t f16_encode_int(int v);
+void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
+                          int64_t p, int64_t q, int stage, int direction, int substrate,
+                          std::vector<uint8_t>& bytes, OperandPlanes& L);
+void build_phaseA_operand(const ModSet& H, std::vector<uint16_t>& out, int* npairs);
+
+}  // namespace obfft

@@ -1,0 +1,128 @@
+"""Exactness and layout of the gfx950 instructions the kernels rely on.
+
+The residue GEMMs need FP8 and INT8 MFMA to accumulate small integers
+exactly, and Phase A needs FP16 MFMA with FP32 accumulation exact below 2^24
+(Sec. 4.2: every column sum stays below 2^24; Sec. 9 item (1d) asks for this
+contract to be measured on the silicon).  Each probe runs one instruction on
+integer operands laid out in the register layout the kernels assume and
+compares with an exact integer matmul.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import e4m3
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_23698_amd import api
+    return api
+
+
+def test_fp8_mfma_16x16x32_layout_and_exactness(gpu):
+    api = _api()
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        A = rng.integers(-16, 17, size=(16, 32))
+        B = rng.integers(-16, 17, size=(32, 16))
+        if trial == 0:
+            A[:] = 16
+            B[:] = 16
+        a = np.zeros((64, 8), np.uint8)
+        b = np.zeros((64, 8), np.uint8)
+        for l in range(64):
+            for j in range(8):
+                k = 8 * (l // 16) + j
+                a[l, j] = e4m3(A[l % 16, k])
+                b[l, j] = e4m3(B[k, l % 16])
+        d = torch.zeros((64, 4), dtype=torch.float32, device=gpu)
+        api.mfma_probe(0, torch.from_numpy(a).to(gpu), torch.from_numpy(b).to(gpu), d)
+        torch.cuda.synchronize()
+        D = d.cpu().numpy()
+        ref = A @ B
+        got = np.zeros((16, 16))
+        for l in range(64):
+            for v in range(4):
+                got[4 * (l // 16) + v, l % 16] = D[l, v]
+        assert np.array_equal(got, ref)
+
+
+def test_i8_mfma_16x16x64_layout_and_exactness(gpu):
+    api = _api()
+    rng = np.random.default_rng(12)
+    A = rng.integers(-128, 128, size=(16, 64))
+    B = rng.integers(-128, 128, size=(64, 16))
+    a = np.zeros((64, 16), np.int8)
+    b = np.zeros((64, 16), np.int8)
+    for l in range(64):
+        for j in range(16):
+            k = 16 * (l // 16) + j
+            a[l, j] = A[l % 16, k]
+            b[l, j] = B[k, l % 16]
+    d = torch.zeros((64, 4), dtype=torch.int32, device=gpu)
+    api.mfma_probe(1, torch.from_numpy(a).to(gpu), torch.from_numpy(b).to(gpu), d)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    got = np.zeros((16, 16), np.int64)
+    for l in range(64):
+        for v in range(4):
+            got[4 * (l // 16) + v, l % 16] = D[l, v]
+    assert np.array_equal(got, A @ B)
+
+
+@pytest.mark.parametrize("extreme", [False, True])
+def test_f16_mfma_32x32x16_layout_and_exactness(gpu, extreme):
+    """Phase-A contract: residues <= 2038 times slices <= 255, 16-term sums, plus 2^23."""
+    api = _api()
+    rng = np.random.default_rng(13)
+    A = rng.integers(0, 256, size=(32, 16))
+    B = rng.integers(0, 2039, size=(16, 32))
+    if extreme:
+        A[:] = 255
+        B[:] = 2038
+    a = np.zeros((64, 8), np.float16)
+    b = np.zeros((64, 8), np.float16)
+    for l in range(64):
+        for j in range(8):
+            k = 8 * (l // 32) + j
+            a[l, j] = A[l % 32, k]
+            b[l, j] = B[k, l % 32]
+    d = torch.zeros((64, 16), dtype=torch.float32, device=gpu)
+    api.mfma_probe(2, torch.from_numpy(a.view(np.int16)).to(gpu), torch.from_numpy(b.view(np.int16)).to(gpu), d)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    got = np.zeros((32, 32), np.int64)
+    for l in range(64):
+        for v in range(16):
+            row = (v % 4) + 8 * (v // 4) + 4 * (l // 32)
+            got[row, l % 32] = D[l, v]
+    assert np.array_equal(got, A @ B)
+
+
+def test_permlane32_swap_semantics(gpu):
+    api = _api()
+    x = torch.arange(64, dtype=torch.int32, device=gpu)
+    y = torch.arange(1000, 1064, dtype=torch.int32, device=gpu)
+    d = torch.zeros(128, dtype=torch.int32, device=gpu)
+    api.mfma_probe(3, x, y, d)
+    torch.cuda.synchronize()
+    out = d.cpu().numpy()
+    nx, ny = out[:64], out[64:]
+    # the upper half of x is exchanged with the lower half of y
+    assert np.array_equal(nx[:32], np.arange(32))
+    assert np.array_equal(nx[32:], np.arange(1000, 1032))
+    assert np.array_equal(ny[:32], np.arange(32, 64))
+    assert np.array_equal(ny[32:], np.arange(1032, 1064))
+
+
+def test_e4m3_conversion_of_small_integers(gpu):
+    api = _api()
+    vals = np.concatenate([np.arange(-16, 17), np.zeros(64 - 33)]).astype(np.float32)
+    d = torch.zeros(64, dtype=torch.uint8, device=gpu)
+    api.mfma_probe(4, torch.from_numpy(vals).to(gpu), None, d)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    ref = np.array([e4m3(v) for v in vals], dtype=np.uint8)
+    assert np.array_equal(got, ref)
