@@ -298,3 +298,35 @@ double oracle_pack_hilo(int64_t hi, uint64_t lo, int exp, int precision) {
   fmt_t f = make_fmt(precision);
   return oracle_pack(v, exp, &f);
 }
+
+/* ---- exported: independent contiguous lines (both stages of one axis pass) ----
+ * Used to time a bounded sample of a large transform: every axis pass of the
+ * 3-D transform is exactly this per-line work on N^2 lines. */
+int oracle_lines(const double* in, double* out, int64_t nlines, int64_t N, int64_t p, int64_t q,
+                 const int64_t* roots, int precision, int nthreads) {
+  if (p * q != N) return -1;
+  if (in != out) memcpy(out, in, sizeof(double) * 2 * nlines * N);
+  if (nthreads < 1) nthreads = 1;
+  int nt = nthreads;
+  if (nt > nlines) nt = (int)nlines;
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nt);
+  axis_job* jobs = (axis_job*)malloc(sizeof(axis_job) * nt);
+  for (int t = 0; t < nt; t++) {
+    jobs[t].data = out;
+    jobs[t].N = N;
+    jobs[t].inner = 1;
+    jobs[t].outer = nlines;
+    jobs[t].line_begin = nlines * t / nt;
+    jobs[t].line_end = nlines * (t + 1) / nt;
+    jobs[t].L.roots = roots;
+    jobs[t].L.N = N;
+    jobs[t].L.p = p;
+    jobs[t].L.q = q;
+    jobs[t].L.f = make_fmt(precision);
+    jobs[t].extra_shift = 0;
+    pthread_create(&th[t], NULL, axis_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  free(th); free(jobs);
+  return 0;
+}

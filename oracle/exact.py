@@ -36,6 +36,9 @@ def lib():
         L.oracle_dd_fft3.restype = ctypes.c_int
         L.oracle_dd_fft3.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _I64P,
                                      ctypes.POINTER(_DP), ctypes.c_int]
+        L.oracle_lines.restype = ctypes.c_int
+        L.oracle_lines.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int64, _I64P, ctypes.c_int, ctypes.c_int]
         L.oracle_pack_hilo.restype = ctypes.c_double
         L.oracle_pack_hilo.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -126,6 +129,20 @@ def line_stage(x, N, p, q, stage, precision=0, inverse=False, extra_shift=0):
     intmin = np.iinfo(np.intc).min
     return {"out": out, "re": _join(rh, rl), "im": _join(ih, il),
             "exp": [None if e == intmin else int(e) for e in ex]}
+
+
+def lines(x, N, p, q, precision=0, inverse=False, nthreads=None):
+    """Both Bailey stages of independent contiguous length-N lines (x: [nlines, N])."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    assert x.shape[-1] == N
+    out = np.empty_like(x)
+    bits = 52 if precision == 0 else 23
+    tab = np.ascontiguousarray(_roots.quantised_roots(N, bits, inverse))
+    rc = lib().oracle_lines(x.ctypes.data, out.ctypes.data, x.size // N, N, p, q, _ptr(tab, _I64P),
+                            precision, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad factorisation")
+    return out
 
 
 def pack(R, exp, precision=0):

@@ -30,6 +30,6 @@ def words_to_int(ws, signed=False):
     v = 0
     for i, w in enumerate(ws):
         v |= (int(w) & 0xFFFFFFFF) << (32 * i)
-    if signed and ws and (int(ws[-1]) & 0x80000000):
+    if signed and len(ws) and (int(ws[-1]) & 0x80000000):
         v -= 1 << (32 * len(ws))
     return v
