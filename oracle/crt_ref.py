@@ -120,16 +120,17 @@ def rne_scaled(R, exp, prec, emin_quantum):
 
 
 def pack_f64(R, exp):
+    """R = 0 gives +0; a nonzero R that rounds to zero keeps its sign (IEEE 754)."""
     q, e = rne_scaled(R, exp, 53, -1074)
     if q == 0:
-        return 0.0
+        return -0.0 if R < 0 else 0.0
     return math.ldexp(float(q), e)
 
 
 def pack_f32(R, exp):
     q, e = rne_scaled(R, exp, 24, -149)
     if q == 0:
-        return 0.0
+        return -0.0 if R < 0 else 0.0
     v = math.ldexp(float(q), e)
     return struct.unpack("<f", struct.pack("<f", v))[0]
 

@@ -152,6 +152,10 @@ def test_pack_is_correctly_rounded_against_python_float():
                 ref = float(Fraction(sgn * R) * Fraction(2) ** e)      # Python: correctly rounded
                 assert crt_ref.pack_f64(sgn * R, e) == ref
                 assert ox.pack(sgn * R, e, 0) == ref                   # the C oracle's pack
+    # a negative value that underflows to zero keeps its sign (IEEE 754 rounding)
+    assert math.copysign(1.0, crt_ref.pack_f32(-2, -200)) == -1.0
+    assert math.copysign(1.0, ox.pack(-2, -200, 1)) == -1.0
+    assert math.copysign(1.0, crt_ref.pack_f64(-1, -1200)) == -1.0
     # binary32 via numpy's correctly rounded float64 -> float32 of exactly representable doubles
     for R in [(1 << 24) + 1, (1 << 24) + 3, (1 << 40) + (1 << 16), 3, (1 << 61) - 1]:
         ref = float(np.float32(Fraction(R) * 1))   # exact Fraction -> RNE float32 via float() first
