@@ -20,6 +20,7 @@ hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* e
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
+int stage_cols_per_wg(int K);
 struct NativePlan;
 NativePlan* native_plan_create(const int64_t* n, std::string& err);
 void native_plan_destroy(NativePlan* np);
@@ -315,7 +316,8 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     P.s_in_s = p * inner;
     P.s_out_g = inner;
     P.s_out_t = p * inner;
-    grid = (P.ncols + kCols - 1) / kCols;
+    int ncw = stage_cols_per_wg(P.K);
+    grid = (P.ncols + ncw - 1) / ncw;
   } else {
     P.K = (int)p;
     P.G = (int)q;
@@ -324,7 +326,8 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     P.s_in_s = inner;
     P.s_out_g = inner;
     P.s_out_t = q * inner;
-    P.tiles_per_g = (int)((P.ncols + kCols - 1) / kCols);
+    int ncw = stage_cols_per_wg(P.K);
+    P.tiles_per_g = (int)((P.ncols + ncw - 1) / ncw);
     grid = (int64_t)P.tiles_per_g * q;
   }
 }

@@ -60,61 +60,85 @@ __host__ __device__ constexpr int chunks_for(int sub, int K) {
   return sub == SUB_INT8 ? (2 * K + 63) / 64 : (4 * K + 31) / 32;
 }
 
-__host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
+__host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
 
-// LDS bytes of one digit buffer.
-__host__ __device__ constexpr int dig_bytes(int sub, int kmax) {
-  return 3 * chunks_for(sub, kmax) * kNT * 64 * (sub == SUB_INT8 ? 16 : 8);
+// Workgroup shape for contraction length K (<= KMAX): MT 16-row M-tiles of
+// the stage matrix and NT 16-column N-tiles, one (M-tile, N-tile) pair per
+// wave, four waves.  K = 32 uses 32 columns so that two workgroups fit in
+// one CU's LDS.
+template <int KMAX>
+struct Shape {
+  static constexpr int MT = (KMAX + 15) / 16;
+  static constexpr int NT = 4 / MT;
+  static constexpr int NCOL = 16 * NT;
+  static constexpr int TPC = kThreads / NCOL;           // threads per column in the decon
+  static constexpr int KQ = (KMAX + TPC - 1) / TPC;     // elements per thread
+};
+
+// Residue records: R fp16 residues per scalar output, 32 records per matrix
+// row (16 columns x Re/Im) plus an 8-byte pad that staggers the LDS banks
+// of neighbouring rows.
+template <int R>
+struct ResLayout {
+  static constexpr int REC = 2 * R;                      // bytes per output
+  static constexpr int ROW = 32 * REC + 8;               // bytes per matrix row of a tile
+};
+
+__host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
+  return 3 * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_INT8 ? 16 : 8);
 }
 
-inline int stage_lds_bytes(int sub, int kq, int K, int R) {
-  int dig = dig_bytes(sub, 4 * kq);
-  int res = align16(kCols * K * 2 * R * 2);
-  return 2 * dig + res + 64 * 8 * 2 + 64 * 4 + 256 * 4;
-}
+template <int SUB, int TGT, int KMAX>
+struct StageLds {
+  typedef Shape<KMAX> SH;
+  static constexpr int R = TGT == 0 ? 12 : 6;
+  static constexpr int DIG = dig_bytes(SUB, KMAX, SH::NT);
+  __host__ __device__ static int res_bytes(int K) { return align16(SH::NT * K * ResLayout<R>::ROW); }
+  __host__ __device__ static int bytes(int K) { return 2 * DIG + res_bytes(K) + SH::NCOL * 20 + kThreads * 4; }
+};
 
-// Writes the digit planes of one residue v (centred, exact integer in FP32)
-// of column jc, contraction index s, Karatsuba form `form` (0: a~, 1: b~,
-// 2: a~ + b~) into the B-operand layout.
-template <int SUB, int CHB>
-__device__ __forceinline__ void put_digits(unsigned char* dig, int form, int jc, int s, float v,
-                                           int nd) {
-  if (SUB == SUB_FP8) {
-    if (nd == 3) {
-      // balanced radix-32 digits, |d| <= 16, exact in E4M3
-      float t1 = __builtin_rintf(v * 0.03125f);
-      float d0 = __builtin_fmaf(-32.0f, t1, v);
-      float t2 = __builtin_rintf(t1 * 0.03125f);
-      float d1 = __builtin_fmaf(-32.0f, t2, t1);
-      uint32_t wd = fp8_pack2<false>(d0, d1, 0u);
-      wd = fp8_pack2<true>(t2, 0.0f, wd);
-      int slot = s * 4, ch = slot >> 5, kk = slot & 31;
-      int ln = (jc & 15) + 16 * (kk >> 3);
-      int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
-      *(uint32_t*)(dig + off) = wd;
-    } else {
-      float t1 = __builtin_rintf(v * 0.03125f);
-      float d0 = __builtin_fmaf(-32.0f, t1, v);
-      uint32_t wd = fp8_pack2<false>(d0, t1, 0u);
-      int slot = s * 2, ch = slot >> 5, kk = slot & 31;
-      int ln = (jc & 15) + 16 * (kk >> 3);
-      int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
-      *(uint16_t*)(dig + off) = (uint16_t)wd;
-    }
+// Writes the digit planes of residue v (exact small integer) of column jc,
+// contraction index s, Karatsuba form `form` (0: a~, 1: b~, 2: a~ + b~).
+template <int SUB, int CHB, int NT>
+__device__ __forceinline__ void put_digits_fp8(unsigned char* dig, int form, int jc, int s, float v, int nd) {
+  if (nd == 3) {
+    // balanced radix-32 digits, |d| <= 16, exact in E4M3
+    float t1 = __builtin_rintf(v * 0.03125f);
+    float d0 = __builtin_fmaf(-32.0f, t1, v);
+    float t2 = __builtin_rintf(t1 * 0.03125f);
+    float d1 = __builtin_fmaf(-32.0f, t2, t1);
+    uint32_t wd = fp8_pack2<false>(d0, d1, 0u);
+    wd = fp8_pack2<true>(t2, 0.0f, wd);
+    int slot = s * 4, ch = slot >> 5, kk = slot & 31;
+    int ln = (jc & 15) + 16 * (kk >> 3);
+    int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
+    *(uint32_t*)(dig + off) = wd;
   } else {
-    // two signed 8-bit limbs, v = d0 + 128 d1, |d0| <= 64, |d1| <= 8
-    float t1 = __builtin_rintf(v * 0.0078125f);
-    float d0 = __builtin_fmaf(-128.0f, t1, v);
-    uint32_t wd = ((uint32_t)(int)d0 & 0xFFu) | (((uint32_t)(int)t1 & 0xFFu) << 8);
-    int slot = s * 2, ch = slot >> 6, kk = slot & 63;
-    int ln = (jc & 15) + 16 * (kk >> 4);
-    int off = (((form * CHB + ch) * kNT + (jc >> 4)) * 64 + ln) * 16 + (kk & 15);
+    float t1 = __builtin_rintf(v * 0.03125f);
+    float d0 = __builtin_fmaf(-32.0f, t1, v);
+    uint32_t wd = fp8_pack2<false>(d0, t1, 0u);
+    int slot = s * 2, ch = slot >> 5, kk = slot & 31;
+    int ln = (jc & 15) + 16 * (kk >> 3);
+    int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
     *(uint16_t*)(dig + off) = (uint16_t)wd;
   }
 }
 
-// Phase A + Phase B for 64 scalar outputs held as canonical residues in LDS
-// or global memory; returns the partials after the lane-half swap.
+// Two signed 8-bit limbs, v = d0 + 128 d1 with d0 in [-64, 63]; |v| <= 2043
+// gives |d1| <= 16.  The limbs are packed into one 16-bit word by v_perm.
+template <int CHB, int NT>
+__device__ __forceinline__ void put_digits_i8(unsigned char* dig, int form, int jc, int s, int v) {
+  int d1 = (v + 64) >> 7;
+  int d0 = v - (d1 << 7);
+  uint32_t wd = __builtin_amdgcn_perm((uint32_t)d1, (uint32_t)d0, 0x0c0c0400u);
+  int slot = s * 2, ch = slot >> 6, kk = slot & 63;
+  int ln = (jc & 15) + 16 * (kk >> 4);
+  int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 16 + (kk & 15);
+  *(uint16_t*)(dig + off) = (uint16_t)wd;
+}
+
+// Phase A for 64 scalar outputs (two 32x32x16 FP16 MFMAs) and the swap that
+// gives every lane all partials of its own output.
 template <int NV>
 __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, float* yv) {
   v16f c;
@@ -131,39 +155,62 @@ __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, floa
   }
 }
 
-template <int SUB, int TGT, int KQ>
+// Phase-A B operand of one lane from a residue record in LDS: moduli
+// 8h .. 8h+7 of the record (zeros beyond r).
+template <int R>
+__device__ __forceinline__ v8h load_record(const unsigned char* rec, int h) {
+  v8h b;
+  if (R == 12) {
+    if (h == 0) {
+      uint2 lo = *(const uint2*)rec;
+      uint2 hi = *(const uint2*)(rec + 8);
+      uint4 w = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      b = __builtin_bit_cast(v8h, w);
+    } else {
+      uint2 lo = *(const uint2*)(rec + 16);
+      uint4 w = make_uint4(lo.x, lo.y, 0u, 0u);
+      b = __builtin_bit_cast(v8h, w);
+    }
+  } else {
+    uint32_t a0 = *(const uint32_t*)rec, a1 = *(const uint32_t*)(rec + 4), a2 = *(const uint32_t*)(rec + 8);
+    uint4 w = h == 0 ? make_uint4(a0, a1, a2, 0u) : make_uint4(0u, 0u, 0u, 0u);
+    b = __builtin_bit_cast(v8h, w);
+  }
+  return b;
+}
+
+template <int SUB, int TGT, int KMAX>
 __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
                                                             const CrtConsts C) {
   typedef Tgt<TGT> TT;
-  typedef SubLayout<SUB> SL;
+  typedef Shape<KMAX> SH;
+  typedef StageLds<SUB, TGT, KMAX> LY;
+  typedef ResLayout<TT::R> RL;
   constexpr int R = TT::R;
-  constexpr int KMAX = 4 * KQ;
-  constexpr int MT = (KMAX + 15) / 16;
-  constexpr int NTW = kNT * MT / 4;
+  constexpr int MT = SH::MT, NT = SH::NT, NCOL = SH::NCOL, TPC = SH::TPC, KQ = SH::KQ;
   constexpr int CHB = chunks_for(SUB, KMAX);
-  constexpr int DIG = dig_bytes(SUB, KMAX);
+  constexpr int DIG = LY::DIG;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int K = P.K;
   unsigned char* dig0 = smem;
   unsigned char* dig1 = smem + DIG;
-  const int res_bytes = align16(kCols * K * 2 * R * 2);
-  uint16_t* res = (uint16_t*)(smem + 2 * DIG);
-  int64_t* col_in = (int64_t*)(smem + 2 * DIG + res_bytes);
-  int64_t* col_out = col_in + 64;
-  int* cexp = (int*)(col_out + 64);
-  int* pexp = cexp + 64;
+  unsigned char* res = smem + 2 * DIG;
+  int64_t* col_in = (int64_t*)(res + LY::res_bytes(K));
+  int64_t* col_out = col_in + NCOL;
+  int* cexp = (int*)(col_out + NCOL);
+  int* pexp = cexp + NCOL;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t g = 0, cstart;
   if (P.stage == 1) {
-    cstart = (int64_t)blockIdx.x * kCols;
+    cstart = (int64_t)blockIdx.x * NCOL;
   } else {
     g = blockIdx.x / P.tiles_per_g;
-    cstart = (int64_t)(blockIdx.x % P.tiles_per_g) * kCols;
+    cstart = (int64_t)(blockIdx.x % P.tiles_per_g) * NCOL;
   }
-  if (tid < 64) {
+  if (tid < NCOL) {
     int64_t c = cstart + tid;
     int64_t ci = -1, co = -1;
     if (c < P.ncols) {
@@ -185,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   __syncthreads();
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
-  const int jc = tid & 63, part = tid >> 6;
+  const int jc = tid % NCOL, part = tid / NCOL;
   const int64_t cin = col_in[jc];
   double ar[KQ], br[KQ];
   int lmax = INT_MIN;
@@ -203,9 +250,11 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
     ar[u] = xr;
     br[u] = xi;
   }
-  pexp[part * 64 + jc] = lmax;
+  pexp[part * NCOL + jc] = lmax;
   __syncthreads();
-  int e = max(max(pexp[jc], pexp[64 + jc]), max(pexp[128 + jc], pexp[192 + jc]));
+  int e = INT_MIN;
+#pragma unroll
+  for (int t = 0; t < TPC; t++) e = max(e, pexp[t * NCOL + jc]);
   if (e == INT_MIN) e = 0;  // all-zero column: every output is zero
   if (part == 0) cexp[jc] = e;
 #pragma unroll
@@ -215,108 +264,111 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   }
 
   const int mt = (MT == 2) ? (wave & 1) : 0;
+  const int nt = (MT == 2) ? (wave >> 1) : wave;
   const uint8_t* amat = P.amat + g * P.amat_g_stride;
+  const int col = nt * 16 + (lane & 15);
 
   for (int i = 0; i < R; i++) {
     unsigned char* dig = (i & 1) ? dig1 : dig0;
     const double md = (double)MC.m[i], imd = MC.inv_md[i];
     const float mf = (float)MC.m[i], imf = MC.inv_mf[i];
     const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
+    const uint8_t* amod = amat + i * P.amat_mod_stride;
+    // A-operand planes of this modulus, issued before the deconstruction so
+    // that their latency overlaps it (INT8: 3 forms x 2 limbs, one chunk).
+    v4i ai8[3][2];
+    if (SUB == SUB_INT8) {
+#pragma unroll
+      for (int form = 0; form < 3; form++)
+#pragma unroll
+        for (int f = 0; f < 2; f++)
+          ai8[form][f] = *(const v4i*)(amod + (((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) *
+                                                  P.amat_chmax * 1024 + lane * 16);
+    }
     // ---- deconstruction: residues and digit planes (Sec. 2, Eq. ozaki) ----
 #pragma unroll
     for (int u = 0; u < KQ; u++) {
       int s = part * KQ + u;
       if (s < K) {
-        float ra = residue_f64(ar[u], md, imd);
-        float rb = residue_f64(br[u], md, imd);
-        float rs = reduce_f32(ra + rb, mf, imf);
-        put_digits<SUB, CHB>(dig, 0, jc, s, ra, nd);
-        put_digits<SUB, CHB>(dig, 1, jc, s, rb, nd);
-        put_digits<SUB, CHB>(dig, 2, jc, s, rs, nd);
+        if (SUB == SUB_INT8) {
+          int ra = (int)__builtin_fma(-md, __builtin_rint(ar[u] * imd), ar[u]);
+          int rb = (int)__builtin_fma(-md, __builtin_rint(br[u] * imd), br[u]);
+          put_digits_i8<CHB, NT>(dig, 0, jc, s, ra);
+          put_digits_i8<CHB, NT>(dig, 1, jc, s, rb);
+          put_digits_i8<CHB, NT>(dig, 2, jc, s, ra + rb);
+        } else {
+          float ra = residue_f64(ar[u], md, imd);
+          float rb = residue_f64(br[u], md, imd);
+          float rs = reduce_f32(ra + rb, mf, imf);
+          put_digits_fp8<SUB, CHB, NT>(dig, 0, jc, s, ra, nd);
+          put_digits_fp8<SUB, CHB, NT>(dig, 1, jc, s, rb, nd);
+          put_digits_fp8<SUB, CHB, NT>(dig, 2, jc, s, rs, nd);
+        }
       }
     }
     __syncthreads();
-    // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) and the combines ----
-    const uint8_t* amod = amat + i * P.amat_mod_stride;
+    // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) ----
+    float Dv[4], Ev[4], Fv[4];
+    if (SUB == SUB_FP8) {
+      const int ndp = nd == 3 ? 4 : 2;
+      const int nch = (ndp * K + 31) >> 5;
+      v4f acc[3][3];
 #pragma unroll
-    for (int w = 0; w < NTW; w++) {
-      const int nt = (MT == 2) ? ((wave >> 1) + 2 * w) : wave;
-      float Dv[4], Ev[4], Fv[4];
-      if (SUB == SUB_FP8) {
-        const int ndp = nd == 3 ? 4 : 2;
-        const int nch = (ndp * K + 31) >> 5;
-        v4f acc[3][3];
+      for (int f = 0; f < 3; f++)
 #pragma unroll
-        for (int f = 0; f < 3; f++)
+        for (int fo = 0; fo < 3; fo++) acc[f][fo] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int fo = 0; fo < 3; fo++) acc[f][fo] = (v4f){0.f, 0.f, 0.f, 0.f};
+      for (int form = 0; form < 3; form++) {
+        for (int ch = 0; ch < nch; ch++) {
+          long bop = *(const long*)(dig + (((form * CHB + ch) * NT + nt) * 64 + lane) * 8);
 #pragma unroll
-        for (int form = 0; form < 3; form++) {
-          for (int ch = 0; ch < nch; ch++) {
-            long bop = *(const long*)(dig + (((form * CHB + ch) * kNT + nt) * 64 + lane) * 8);
-#pragma unroll
-            for (int f = 0; f < 3; f++) {
-              if (f < nd) {
-                const uint8_t* ap =
-                    amod + ((((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) * P.amat_chmax + ch) * 512 +
-                    lane * 8;
-                long aop = *(const long*)ap;
-                acc[form][f] = mfma_fp8(aop, bop, acc[form][f]);
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          Dv[v] = __builtin_fmaf(1024.0f, acc[0][2][v], __builtin_fmaf(32.0f, acc[0][1][v], acc[0][0][v]));
-          Ev[v] = __builtin_fmaf(1024.0f, acc[1][2][v], __builtin_fmaf(32.0f, acc[1][1][v], acc[1][0][v]));
-          Fv[v] = __builtin_fmaf(1024.0f, acc[2][2][v], __builtin_fmaf(32.0f, acc[2][1][v], acc[2][0][v]));
-        }
-      } else {
-        v4i acc[3][2];
-#pragma unroll
-        for (int f = 0; f < 3; f++)
-#pragma unroll
-          for (int fo = 0; fo < 2; fo++) acc[f][fo] = (v4i){0, 0, 0, 0};
-        const int nch = (2 * K + 63) >> 6;
-#pragma unroll
-        for (int form = 0; form < 3; form++) {
-          for (int ch = 0; ch < nch; ch++) {
-            v4i bop = *(const v4i*)(dig + (((form * CHB + ch) * kNT + nt) * 64 + lane) * 16);
-#pragma unroll
-            for (int f = 0; f < 2; f++) {
+          for (int f = 0; f < 3; f++) {
+            if (f < nd) {
               const uint8_t* ap =
-                  amod + ((((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) * P.amat_chmax + ch) * 1024 +
-                  lane * 16;
-              v4i aop = *(const v4i*)ap;
-              acc[form][f] = mfma_i8(aop, bop, acc[form][f]);
+                  amod + ((((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) * P.amat_chmax + ch) * 512 +
+                  lane * 8;
+              acc[form][f] = mfma_fp8(*(const long*)ap, bop, acc[form][f]);
             }
           }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          Dv[v] = (float)(acc[0][0][v] + (acc[0][1][v] << 7));
-          Ev[v] = (float)(acc[1][0][v] + (acc[1][1][v] << 7));
-          Fv[v] = (float)(acc[2][0][v] + (acc[2][1][v] << 7));
         }
       }
-      const int col = nt * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int row = 16 * mt + 4 * (lane >> 4) + v;
-        if (row < K) {
-          float rr = canonical_f32(Dv[v] - Ev[v], mf, imf);
-          float ri = canonical_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
-          int id = ((nt * K + row) * 16 + (lane & 15)) * 2;
-          res[id * R + i] = __builtin_bit_cast(uint16_t, (_Float16)rr);
-          res[(id + 1) * R + i] = __builtin_bit_cast(uint16_t, (_Float16)ri);
-          if (P.dbg_res) {
-            int64_t co = col_out[col];
-            if (co >= 0) {
-              int64_t el = co + (int64_t)row * P.s_out_t;
-              P.dbg_res[(el * 2) * R + i] = (uint16_t)rr;
-              P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)ri;
-            }
+        Dv[v] = __builtin_fmaf(1024.0f, acc[0][2][v], __builtin_fmaf(32.0f, acc[0][1][v], acc[0][0][v]));
+        Ev[v] = __builtin_fmaf(1024.0f, acc[1][2][v], __builtin_fmaf(32.0f, acc[1][1][v], acc[1][0][v]));
+        Fv[v] = __builtin_fmaf(1024.0f, acc[2][2][v], __builtin_fmaf(32.0f, acc[2][1][v], acc[2][0][v]));
+      }
+    } else {
+      v4i acc[3][2];
+#pragma unroll
+      for (int form = 0; form < 3; form++) {
+        v4i bop = *(const v4i*)(dig + (((form * CHB) * NT + nt) * 64 + lane) * 16);
+#pragma unroll
+        for (int f = 0; f < 2; f++) acc[form][f] = mfma_i8(ai8[form][f], bop, (v4i){0, 0, 0, 0});
+      }
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        Dv[v] = (float)(acc[0][0][v] + (acc[0][1][v] << 7));
+        Ev[v] = (float)(acc[1][0][v] + (acc[1][1][v] << 7));
+        Fv[v] = (float)(acc[2][0][v] + (acc[2][1][v] << 7));
+      }
+    }
+    // ---- residue-domain combines, canonical residues to the records ----
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int row = 16 * mt + 4 * (lane >> 4) + v;
+      if (row < K) {
+        float rr = canonical_f32(Dv[v] - Ev[v], mf, imf);
+        float ri = canonical_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+        unsigned char* rrow = res + (nt * K + row) * RL::ROW;
+        *(_Float16*)(rrow + (lane & 15) * RL::REC + 2 * i) = (_Float16)rr;
+        *(_Float16*)(rrow + (16 + (lane & 15)) * RL::REC + 2 * i) = (_Float16)ri;
+        if (P.dbg_res) {
+          int64_t co = col_out[col];
+          if (co >= 0) {
+            int64_t el = co + (int64_t)row * P.s_out_t;
+            P.dbg_res[(el * 2) * R + i] = (uint16_t)rr;
+            P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)ri;
           }
         }
       }
@@ -325,19 +377,18 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   __syncthreads();
 
   // ---- Phase A (FP16 MFMA) + Phase B (Kulisch, lift, pack) ----
+  // Batch b = (N-tile, row pair); lane o of the batch owns output
+  // (row 2rp + o/32, column (o/2) % 16, Re/Im o % 2).
   v8h aop = *(const v8h*)(P.phaseA + lane * 8);
   const int h = lane >> 5;
-  const int nbatch = kNT * K / 2;
+  const int nbatch = NT * K / 2;
+  const int o = lane & 31;
+  const int ocol = o >> 1, oprt = o & 1;
   for (int b = wave; b < nbatch; b += 4) {
-    const int nt = b / (K / 2), rp = b % (K / 2);
-    const int id1 = (nt * K + 2 * rp) * 32 + (lane & 31);
-    v8h b1, b2;
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      int k = 8 * h + j;
-      b1[j] = k < R ? __builtin_bit_cast(_Float16, res[id1 * R + k]) : (_Float16)0.0f;
-      b2[j] = k < R ? __builtin_bit_cast(_Float16, res[(id1 + 32) * R + k]) : (_Float16)0.0f;
-    }
+    const int bt = b / (K / 2), rp = b % (K / 2);
+    const unsigned char* r1 = res + (bt * K + 2 * rp) * RL::ROW + (oprt * 16 + ocol) * RL::REC;
+    v8h b1 = load_record<R>(r1, h);
+    v8h b2 = load_record<R>(r1 + RL::ROW, h);
     float xv[EP::NV], yv[EP::NV];
     phase_a<EP::NV>(aop, b1, b2, xv, yv);
     uint32_t wv[(TT::S + 3) / 4 + 1];
@@ -346,17 +397,17 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
     uint32_t Rw[TT::NW];
     EP::lift(wv, zh, C, Rw);
     const int row = 2 * rp + (lane >> 5);
-    const int col = nt * 16 + ((lane >> 1) & 15);
+    const int c = bt * 16 + ((lane >> 1) & 15);
     const int prt = lane & 1;
-    const int64_t co = col_out[col];
+    const int64_t co = col_out[c];
     if (co >= 0 && row < K) {
-      const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
-      typename TT::T* o = (typename TT::T*)P.out;
+      const int ex = cexp[c] - 2 * (TT::PREC - 1) + P.extra_shift;
+      typename TT::T* op = (typename TT::T*)P.out;
       int64_t idx = (co + (int64_t)row * P.s_out_t) * 2 + prt;
       if (TGT == 0)
-        o[idx] = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
+        op[idx] = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
       else
-        o[idx] = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
+        op[idx] = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
     }
   }
 }
@@ -457,18 +508,18 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
 }
 
 // ---- host-side launch helpers ----
-template <int SUB, int TGT, int KQ>
+template <int SUB, int TGT, int KMAX>
 static hipError_t launch_stage_t(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
                                  int64_t grid, hipStream_t st) {
-  int lds = stage_lds_bytes(SUB, KQ, P.K, Tgt<TGT>::R);
+  int lds = StageLds<SUB, TGT, KMAX>::bytes(P.K);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KQ>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KQ>), dim3((unsigned)grid), dim3(kThreads), lds, st, P,
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, P,
                      MC, C);
   return hipGetLastError();
 }
@@ -477,11 +528,11 @@ template <int SUB, int TGT>
 static hipError_t launch_stage_k(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
                                  int64_t grid, hipStream_t st) {
   int K = P.K;
-  if (K <= 4) return launch_stage_t<SUB, TGT, 1>(P, MC, C, grid, st);
-  if (K <= 8) return launch_stage_t<SUB, TGT, 2>(P, MC, C, grid, st);
-  if (K <= 12) return launch_stage_t<SUB, TGT, 3>(P, MC, C, grid, st);
-  if (K <= 16) return launch_stage_t<SUB, TGT, 4>(P, MC, C, grid, st);
-  return launch_stage_t<SUB, TGT, 8>(P, MC, C, grid, st);
+  if (K <= 4) return launch_stage_t<SUB, TGT, 4>(P, MC, C, grid, st);
+  if (K <= 8) return launch_stage_t<SUB, TGT, 8>(P, MC, C, grid, st);
+  if (K <= 12) return launch_stage_t<SUB, TGT, 12>(P, MC, C, grid, st);
+  if (K <= 16) return launch_stage_t<SUB, TGT, 16>(P, MC, C, grid, st);
+  return launch_stage_t<SUB, TGT, 32>(P, MC, C, grid, st);
 }
 
 hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
@@ -493,10 +544,8 @@ hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts&
                   : launch_stage_k<SUB_FP8, 1>(P, MC, C, grid, st);
 }
 
-int stage_lds_bytes_for(int sub, int K, int tgt) {
-  int kq = K <= 4 ? 1 : K <= 8 ? 2 : K <= 12 ? 3 : K <= 16 ? 4 : 8;
-  return stage_lds_bytes(sub, kq, K, tgt == 0 ? 12 : 6);
-}
+// Columns per workgroup of the stage kernel for contraction length K.
+int stage_cols_per_wg(int K) { return K <= 16 ? Shape<16>::NCOL : Shape<32>::NCOL; }
 
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts& C, hipStream_t st) {

@@ -6,8 +6,6 @@ namespace obfft {
 
 constexpr int kMaxModuli = 16;
 constexpr int kMaxK = 32;          // longest contraction (p or q) of the fused stage kernel
-constexpr int kNT = 4;             // 16-column N-tiles per workgroup
-constexpr int kCols = 16 * kNT;    // columns per workgroup
 constexpr int kThreads = 256;      // 4 waves of 64
 constexpr int kTapStride = 40;     // uint32 words per output in the CRT debug taps
 
