@@ -189,13 +189,20 @@ typedef struct {
 } obfft_crt_constants_t;
 obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
 
-/* Batched transforms: `count` independent FP64 transforms of possibly
- * different shapes, executed by one persistent kernel per Bailey pass.
- * shapes: host int64 [count][3].  ins/outs: host arrays of device pointers. */
+/* Batched transforms: `count` independent FP64 forward transforms of possibly
+ * different shapes (host int64 [count][3]).  Each of the six Bailey passes
+ * (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs as ONE persistent
+ * launch over the tiles of every member; the six launches are captured once
+ * in a hipGraph and replayed.  Members with equal shapes share one plan.
+ * Outputs are bit-identical to fft3d_z2z_forward on each member.  The batch
+ * owns a workspace of the summed member sizes, allocated on first use.
+ * ins/outs: host arrays of `count` device pointers. */
 obfft_status_t obfft_batch_plan_create(obfft_plan_t* plan, int count, const int64_t* shapes,
                                        const obfft_options_t* opt);
 obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
                                    void* stream);
+/* use_graph = 0 launches the six passes directly instead of replaying the graph. */
+obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph);
 
 const char* obfft_status_string(obfft_status_t status);
 /* The status of the last failed call on this plan (OBFFT_SUCCESS if none). */

@@ -330,3 +330,83 @@ int oracle_lines(const double* in, double* out, int64_t nlines, int64_t N, int64
   free(th); free(jobs);
   return 0;
 }
+
+/* ---- exported: one output position k of every line (the cost cone) ----
+ * Output k = k2 + q k1 of a line needs, from stage 1, the k2-th output of
+ * every column j1 (each column still needs all its elements for its
+ * exponent), then one stage-2 contraction.  Same definitions as above,
+ * evaluated only where the sampled output depends on them. */
+typedef struct {
+  const double* in;
+  double* out;
+  int64_t N, k, begin, end;
+  line_ctx L;
+} cone_job;
+
+static void contract_one(const line_ctx* L, int stage, int64_t g, const double* col, int64_t K,
+                         int64_t t, double* out2) {
+  int e;
+  if (!column_exponent(col, K, 1, &e)) { out2[0] = 0.0; out2[1] = 0.0; return; }
+  int qshift = (L->f.prec - 1) - e;
+  int pexp = e - (L->f.prec - 1) - L->f.tbits;
+  i128 D = 0, E = 0, F = 0;
+  for (int64_t s = 0; s < K; s++) {
+    int64_t a = quantise(col[2 * s], qshift), b = quantise(col[2 * s + 1], qshift);
+    int64_t idx = stage == 1 ? (L->p * s * t) % L->N : (s * (g + L->q * t)) % L->N;
+    int64_t c = L->roots[2 * idx], sn = L->roots[2 * idx + 1];
+    D += (i128)c * a;
+    E += (i128)sn * b;
+    F += (i128)(c + sn) * (i128)(a + b);
+  }
+  out2[0] = oracle_pack(D - E, pexp, &L->f);
+  out2[1] = oracle_pack(F - D - E, pexp, &L->f);
+}
+
+static void* cone_worker(void* arg) {
+  cone_job* J = (cone_job*)arg;
+  const line_ctx* L = &J->L;
+  int64_t N = J->N, p = L->p, q = L->q;
+  int64_t k2 = J->k % q, k1 = J->k / q;
+  double* col = (double*)malloc(sizeof(double) * 2 * (p > q ? p : q));
+  double* y = (double*)malloc(sizeof(double) * 2 * p);
+  for (int64_t line = J->begin; line < J->end; line++) {
+    const double* X = J->in + 2 * N * line;
+    for (int64_t j1 = 0; j1 < p; j1++) {
+      for (int64_t j2 = 0; j2 < q; j2++) {
+        col[2 * j2] = X[2 * (j1 + p * j2)];
+        col[2 * j2 + 1] = X[2 * (j1 + p * j2) + 1];
+      }
+      contract_one(L, 1, j1, col, q, k2, y + 2 * j1);
+    }
+    contract_one(L, 2, k2, y, p, k1, J->out + 2 * line);
+  }
+  free(col); free(y);
+  return NULL;
+}
+
+int oracle_lines_at(const double* in, double* out, int64_t nlines, int64_t N, int64_t p, int64_t q,
+                    const int64_t* roots, int precision, int64_t k, int nthreads) {
+  if (p * q != N || k < 0 || k >= N) return -1;
+  if (nthreads < 1) nthreads = 1;
+  int nt = nthreads;
+  if (nt > nlines) nt = (int)nlines;
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nt);
+  cone_job* jobs = (cone_job*)malloc(sizeof(cone_job) * nt);
+  for (int t = 0; t < nt; t++) {
+    jobs[t].in = in;
+    jobs[t].out = out;
+    jobs[t].N = N;
+    jobs[t].k = k;
+    jobs[t].begin = nlines * t / nt;
+    jobs[t].end = nlines * (t + 1) / nt;
+    jobs[t].L.roots = roots;
+    jobs[t].L.N = N;
+    jobs[t].L.p = p;
+    jobs[t].L.q = q;
+    jobs[t].L.f = make_fmt(precision);
+    pthread_create(&th[t], NULL, cone_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  free(th); free(jobs);
+  return 0;
+}

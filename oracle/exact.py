@@ -39,6 +39,10 @@ def lib():
         L.oracle_lines.restype = ctypes.c_int
         L.oracle_lines.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int64, ctypes.c_int64, _I64P, ctypes.c_int, ctypes.c_int]
+        L.oracle_lines_at.restype = ctypes.c_int
+        L.oracle_lines_at.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, _I64P, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_int]
         L.oracle_pack_hilo.restype = ctypes.c_double
         L.oracle_pack_hilo.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -142,6 +146,20 @@ def lines(x, N, p, q, precision=0, inverse=False, nthreads=None):
                             precision, nthreads or default_threads())
     if rc != 0:
         raise ValueError("bad factorisation")
+    return out
+
+
+def lines_at(x, N, p, q, k, precision=0, inverse=False, nthreads=None):
+    """Output position k of both Bailey stages of every contiguous line of x ([nlines, N])."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    nl = x.size // N
+    out = np.empty(nl, dtype=np.complex128)
+    bits = 52 if precision == 0 else 23
+    tab = np.ascontiguousarray(_roots.quantised_roots(N, bits, inverse))
+    rc = lib().oracle_lines_at(x.ctypes.data, out.ctypes.data, nl, N, p, q, _ptr(tab, _I64P),
+                               precision, k, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad factorisation or position")
     return out
 
 

@@ -72,6 +72,7 @@ def lib():
         "obfft_crt_constants": (i32, [i32, P(CrtConstants)]),
         "obfft_batch_plan_create": (i32, [P(vp), i32, P(i64), P(Options)]),
         "obfft_batch_forward": (i32, [vp, P(vp), P(vp), vp]),
+        "obfft_batch_set_graph": (i32, [vp, i32]),
         "obfft_status_string": (ctypes.c_char_p, [i32]),
         "obfft_last_error": (i32, [vp]),
     }
@@ -101,4 +102,4 @@ EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", 
             "fft3d_z2z_native_forward", "fft3d_z2z_native_inverse", "obfft_stage",
             "obfft_crt_reconstruct", "obfft_taps_layout", "obfft_mfma_probe",
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
-            "obfft_batch_forward", "obfft_status_string", "obfft_last_error"]
+            "obfft_batch_forward", "obfft_batch_set_graph", "obfft_status_string", "obfft_last_error"]

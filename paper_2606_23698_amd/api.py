@@ -25,6 +25,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _materialise(t):
+    """Resolve torch's lazy conjugate / negative views: the kernels read raw memory."""
+    if isinstance(t, torch.Tensor):
+        if t.is_conj():
+            t = t.resolve_conj()
+        if t.is_neg():
+            t = t.resolve_neg()
+    return t
+
+
 def _check_dev(t, dtype, numel=None, name="tensor"):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
@@ -101,6 +111,7 @@ class Plan:
         self._ws = ws
 
     def _run(self, fname, x, out, stream):
+        x = _materialise(x)
         _check_dev(x, self.cdtype, name="input")
         if tuple(x.shape) != self.shape:
             raise ValueError(f"input shape {tuple(x.shape)} != plan shape {self.shape}")
@@ -129,6 +140,7 @@ class Plan:
 
     def stage(self, axis, stage, x, out=None, direction=0, residues=None, stream=None):
         """One Bailey stage of one axis; residues (int16 [numel, 2, r]) receives the tap."""
+        x = _materialise(x)
         _check_dev(x, self.cdtype, name="input")
         if out is None:
             out = torch.empty_like(x)
@@ -155,9 +167,13 @@ class BatchPlan:
                                                 ctypes.byref(opt)), "obfft_batch_plan_create")
         self._h = h
 
+    def set_graph(self, use_graph):
+        L.check(L.lib().obfft_batch_set_graph(self._h, int(bool(use_graph))), "obfft_batch_set_graph")
+
     def forward(self, xs, outs=None, stream=None):
         if len(xs) != len(self.shapes):
             raise ValueError("wrong number of inputs")
+        xs = [_materialise(x) for x in xs]
         if outs is None:
             outs = [torch.empty_like(x) for x in xs]
         for x, o, s in zip(xs, outs, self.shapes):

@@ -21,6 +21,8 @@ hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
 int stage_cols_per_wg(int K);
+hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* prefix, int ndesc,
+                        int64_t grid, const ModConsts& MC, const CrtConsts& C, hipStream_t st);
 struct NativePlan;
 NativePlan* native_plan_create(const int64_t* n, std::string& err);
 void native_plan_destroy(NativePlan* np);
@@ -55,7 +57,21 @@ struct obfft_plan_s {
   int device = 0;
   // batch plans
   int batch_count = 0;
-  std::vector<obfft_plan_t> members;
+  std::vector<obfft_plan_t> members;          // owned, one per distinct shape
+  std::vector<obfft_plan_t> members_of_batch; // per batch entry (borrowed)
+  int batch_kmax = 0;
+  StageParams* d_desc = nullptr;      // device [6][count]
+  StageParams* h_desc = nullptr;      // pinned host staging [6][count]
+  int64_t* d_prefix = nullptr;        // device [6][count + 1]
+  int64_t batch_total[6] = {0, 0, 0, 0, 0, 0};
+  void* batch_ws = nullptr;
+  std::vector<size_t> ws_off;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipEvent_t desc_done = nullptr;     // the last descriptor upload has left the pinned buffer
+  int64_t batch_grid[6] = {0, 0, 0, 0, 0, 0};
+  bool use_graph = true;
 };
 
 static obfft_status_t fail(obfft_plan_t plan, obfft_status_t s) {
@@ -225,6 +241,14 @@ extern "C" obfft_status_t obfft_plan_create(obfft_plan_t* out, int64_t n1, int64
 extern "C" obfft_status_t obfft_plan_destroy(obfft_plan_t plan) {
   if (!plan) return OBFFT_INVALID_VALUE;
   for (auto m : plan->members) obfft_plan_destroy(m);
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+  if (plan->desc_done) (void)hipEventDestroy(plan->desc_done);
+  if (plan->d_desc) (void)hipFree(plan->d_desc);
+  if (plan->d_prefix) (void)hipFree(plan->d_prefix);
+  if (plan->h_desc) (void)hipHostFree(plan->h_desc);
+  if (plan->batch_ws) (void)hipFree(plan->batch_ws);
   for (void* d : plan->dev_allocs) hipFree(d);
   if (plan->ws_owned && plan->ws) hipFree(plan->ws);
   if (plan->native) native_plan_destroy(plan->native);
@@ -503,36 +527,171 @@ extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* 
 }
 
 // ---- batched transforms ----
+//
+// All member transforms of a batch run pass by pass (axis n3 stage 1, n3
+// stage 2, n2 ..., n1 stage 2): each pass is ONE persistent launch over the
+// tiles of every member, driven by a device table of stage descriptors.  The
+// six launches are captured once in a hipGraph and replayed; only the table
+// (with the callers' pointers) is re-uploaded per call.
+static const int kPassAxis[6] = {2, 2, 1, 1, 0, 0};
+static const int kPassStage[6] = {1, 2, 1, 2, 1, 2};
+
 extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
                                                   const obfft_options_t* opt) {
   if (!out || count <= 0 || !shapes) return OBFFT_INVALID_VALUE;
   *out = nullptr;
+  obfft_options_t def;
+  obfft_options_default(&def);
+  if (!opt) opt = &def;
+  if (opt->precision != OBFFT_PREC_FP64) return OBFFT_INVALID_VALUE;
   obfft_plan_t bp = new (std::nothrow) obfft_plan_s();
   if (!bp) return OBFFT_ALLOC_FAILED;
   bp->batch_count = count;
+  // members share planes when their shapes coincide: plan each distinct shape once
+  std::map<std::tuple<int64_t, int64_t, int64_t>, obfft_plan_t> uniq;
+  std::vector<obfft_plan_t> per(count);
   for (int i = 0; i < count; i++) {
-    obfft_plan_t m = nullptr;
-    obfft_status_t s = obfft_plan_create(&m, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2], opt);
-    if (s != OBFFT_SUCCESS) {
-      obfft_plan_destroy(bp);
-      return s;
+    auto key = std::make_tuple(shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
+    auto it = uniq.find(key);
+    if (it == uniq.end()) {
+      obfft_plan_t m = nullptr;
+      obfft_status_t s = obfft_plan_create(&m, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2], opt);
+      if (s != OBFFT_SUCCESS) {
+        obfft_plan_destroy(bp);
+        return s;
+      }
+      bp->members.push_back(m);
+      it = uniq.emplace(key, m).first;
     }
-    bp->members.push_back(m);
+    per[i] = it->second;
   }
+  bp->substrate = per[0]->substrate;
+  bp->precision = OBFFT_PREC_FP64;
+  bp->MC = per[0]->MC;
+  bp->C = per[0]->C;
+  int kmax = 0;
+  for (int i = 0; i < count; i++)
+    for (int a = 0; a < 3; a++) kmax = std::max(kmax, std::max(per[i]->p[a], per[i]->q[a]));
+  bp->batch_kmax = kmax <= 16 ? 16 : 32;
+  const int ncol = stage_cols_per_wg(bp->batch_kmax);
+  // workspace offsets (256-byte aligned)
+  size_t off = 0;
+  bp->ws_off.resize(count);
+  for (int i = 0; i < count; i++) {
+    bp->ws_off[i] = off;
+    off += (per[i]->ws_bytes + 255) & ~(size_t)255;
+  }
+  bp->ws_bytes = off;
+  // descriptors without pointers, prefix sums of tiles
+  size_t dbytes = sizeof(StageParams) * 6 * count;
+  if (hipHostMalloc((void**)&bp->h_desc, dbytes, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&bp->d_desc, dbytes) != hipSuccess ||
+      hipMalloc((void**)&bp->d_prefix, sizeof(int64_t) * 6 * (count + 1)) != hipSuccess) {
+    obfft_plan_destroy(bp);
+    return OBFFT_ALLOC_FAILED;
+  }
+  std::vector<int64_t> prefix(6 * (count + 1));
+  for (int pass = 0; pass < 6; pass++) {
+    int64_t acc = 0;
+    for (int i = 0; i < count; i++) {
+      StageParams& P = bp->h_desc[pass * count + i];
+      int64_t grid;
+      stage_params(per[i], kPassAxis[pass], kPassStage[pass], 0, nullptr, nullptr, P, grid);
+      // tiles on the batch kernel's shape
+      if (P.stage == 1) {
+        grid = (P.ncols + ncol - 1) / ncol;
+      } else {
+        P.tiles_per_g = (int)((P.ncols + ncol - 1) / ncol);
+        grid = (int64_t)P.tiles_per_g * P.G;
+      }
+      prefix[pass * (count + 1) + i] = acc;
+      acc += grid;
+    }
+    prefix[pass * (count + 1) + count] = acc;
+    bp->batch_total[pass] = acc;
+  }
+  if (hipMemcpy(bp->d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice) !=
+      hipSuccess || hipEventCreateWithFlags(&bp->desc_done, hipEventDisableTiming) != hipSuccess) {
+    obfft_plan_destroy(bp);
+    return OBFFT_HIP_ERROR;
+  }
+  int dev = 0, ncu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    ncu = prop.multiProcessorCount;
+  for (int pass = 0; pass < 6; pass++) bp->batch_grid[pass] = std::min<int64_t>(bp->batch_total[pass], (int64_t)ncu * 8);
+  bp->members_of_batch = per;
   *out = bp;
+  return OBFFT_SUCCESS;
+}
+
+static obfft_status_t batch_launch_passes(obfft_plan_t bp, hipStream_t st) {
+  int count = bp->batch_count;
+  for (int pass = 0; pass < 6; pass++) {
+    int64_t grid = bp->batch_grid[pass];
+    if (grid <= 0) continue;
+    if (launch_batch(bp->substrate, bp->batch_kmax, bp->d_desc + pass * count, bp->d_prefix + pass * (count + 1),
+                     count, grid, bp->MC, bp->C, st) != hipSuccess)
+      return OBFFT_HIP_ERROR;
+  }
   return OBFFT_SUCCESS;
 }
 
 extern "C" obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
                                               void* stream) {
   if (!plan || !plan->batch_count || !ins || !outs) return OBFFT_INVALID_VALUE;
-  for (int i = 0; i < plan->batch_count; i++) {
-    obfft_status_t s = fft3d_z2z_forward(plan->members[i], ins[i], outs[i], stream);
-    if (s != OBFFT_SUCCESS) return fail(plan, s);
+  int count = plan->batch_count;
+  hipStream_t st = (hipStream_t)stream;
+  if (!plan->batch_ws) {
+    if (hipMalloc(&plan->batch_ws, std::max<size_t>(plan->ws_bytes, 256)) != hipSuccess)
+      return fail(plan, OBFFT_ALLOC_FAILED);
   }
+  // the previous call's upload must have left the pinned staging buffer
+  if (hipEventSynchronize(plan->desc_done) != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
+  for (int i = 0; i < count; i++) {
+    obfft_plan_t m = plan->members_of_batch[i];
+    size_t bytes = (size_t)(m->n[0] * m->n[1] * m->n[2]) * 16;
+    if (!ins[i] || !outs[i] || overlaps(ins[i], outs[i], bytes)) return fail(plan, OBFFT_INVALID_VALUE);
+    void* ws = (char*)plan->batch_ws + plan->ws_off[i];
+    const void* cur = ins[i];
+    for (int pass = 0; pass < 6; pass++) {
+      StageParams& P = plan->h_desc[pass * count + i];
+      bool s1 = kPassStage[pass] == 1;
+      P.in = s1 ? cur : ws;
+      P.out = s1 ? ws : outs[i];
+      if (!s1) cur = outs[i];
+    }
+  }
+  if (hipMemcpyAsync(plan->d_desc, plan->h_desc, sizeof(StageParams) * 6 * count, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipEventRecord(plan->desc_done, st) != hipSuccess)
+    return fail(plan, OBFFT_HIP_ERROR);
+  if (!plan->use_graph) return fail(plan, batch_launch_passes(plan, st));
+  if (!plan->graph_exec) {
+    if (!plan->capture_stream && hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(plan, OBFFT_HIP_ERROR);
+    if (hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(plan, OBFFT_HIP_ERROR);
+    obfft_status_t s = batch_launch_passes(plan, plan->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(plan->capture_stream, &g);
+    if (s != OBFFT_SUCCESS || e != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
+    plan->graph = g;
+    if (hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0) != hipSuccess)
+      return fail(plan, OBFFT_HIP_ERROR);
+  }
+  if (hipGraphLaunch(plan->graph_exec, st) != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
   return OBFFT_SUCCESS;
 }
 
+// Selects graph replay (1, default) or direct launches (0) for a batch plan.
+extern "C" obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph) {
+  if (!plan || !plan->batch_count) return OBFFT_INVALID_VALUE;
+  plan->use_graph = use_graph != 0;
+  return OBFFT_SUCCESS;
+}
+
+// Workspace of the batch (sum of the members', 256-byte aligned).
 // ---- host-only introspection (no device needed) ----
 extern "C" obfft_status_t obfft_quantised_roots(int64_t N, int bits, int64_t* host_out) {
   if (N < 1 || bits < 1 || bits > 61 || !host_out) return OBFFT_INVALID_VALUE;

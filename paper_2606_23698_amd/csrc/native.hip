@@ -183,6 +183,194 @@ __global__ __launch_bounds__(kNatThreads) void native_axis_kernel(const double2*
   }
 }
 
+// ---- register-resident four-step kernel: N = R1 x R2, R1 <= R2 <= 32 ----
+//
+// Line element n = n1 R2 + n2, output k = k1 + R1 k2 (Cooley-Tukey):
+//   step 1: thread (line, n2) loads x[n1 R2 + n2], n1 < R1, does DFT_R1 over n1
+//           in registers and multiplies by w_N^{n2 k1};
+//   exchange through LDS (real plane, then imaginary plane);
+//   step 2: thread (line, k1) does DFT_R2 over n2 in registers and stores
+//           X[k1 + R1 k2], k2 < R2.
+// STRIDED selects the lane mapping: false (contiguous axis) puts neighbouring
+// lanes along a line, true puts them on neighbouring lines, so that global
+// loads and stores are coalesced in both cases.
+
+// Length-R DFT in registers, decimation in time with radix 2 or 3 steps;
+// twiddles w_R^t are read from `tw` (the axis table w_N^t) at stride N/R.
+template <int R, int DIR>
+struct RegDft {
+  __device__ __forceinline__ static void run(double2* v, const double2* tw, int tstride) {
+    if constexpr (R == 1) {
+      return;
+    } else {
+      constexpr int r = (R % 2 == 0) ? 2 : 3;
+      constexpr int m = R / r;
+      double2 sub[r][m];
+#pragma unroll
+      for (int a = 0; a < r; a++)
+#pragma unroll
+        for (int j = 0; j < m; j++) sub[a][j] = v[a + r * j];
+#pragma unroll
+      for (int a = 0; a < r; a++) RegDft<m, DIR>::run(sub[a], tw, tstride * r);
+#pragma unroll
+      for (int k = 0; k < m; k++) {
+#pragma unroll
+        for (int b = 0; b < r; b++) {
+          double2 acc = sub[0][k];
+#pragma unroll
+          for (int a = 1; a < r; a++) {
+            const int t = (a * (k + m * b)) % R;
+            double2 x = sub[a][k];
+            if (t == 0) {
+              acc.x += x.x;
+              acc.y += x.y;
+            } else if (2 * t == R) {
+              acc.x -= x.x;
+              acc.y -= x.y;
+            } else if (4 * t == R) {
+              // w = -i DIR
+              acc.x += DIR * x.y;
+              acc.y -= DIR * x.x;
+            } else if (4 * t == 3 * R) {
+              acc.x -= DIR * x.y;
+              acc.y += DIR * x.x;
+            } else {
+              double2 w = tw[t * tstride];
+              double wy = DIR * w.y;
+              acc.x = __builtin_fma(x.x, w.x, __builtin_fma(-x.y, wy, acc.x));
+              acc.y = __builtin_fma(x.x, wy, __builtin_fma(x.y, w.x, acc.y));
+            }
+          }
+          v[k + m * b] = acc;
+        }
+      }
+    }
+  }
+};
+
+template <int R1, int R2, bool STRIDED, int DIR>
+__global__ __launch_bounds__(kNatThreads) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
+                                                                   int64_t nlines, const double2* tw,
+                                                                   double post_scale) {
+  constexpr int N = R1 * R2;
+  constexpr int LPW = kNatThreads / R2;           // lines per workgroup
+  constexpr int LS = ((R1 * (R2 + 1)) | 1);      // padded line stride in LDS (doubles, odd)
+  __shared__ double plane[LPW * LS];
+  const int tid = threadIdx.x;
+  const int64_t line0 = (int64_t)blockIdx.x * LPW;
+  // step 1 mapping
+  int l1, n2;
+  if (STRIDED) {
+    l1 = tid % LPW;
+    n2 = tid / LPW;
+  } else {
+    n2 = tid % R2;
+    l1 = tid / R2;
+  }
+  const int64_t L = line0 + l1;
+  const bool valid1 = L < nlines;
+  const int64_t o1 = L / inner, i1 = L % inner;
+  const double2* src = in + o1 * N * inner + i1;
+  double2 v[R1];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; n1++)
+    v[n1] = valid1 ? src[(int64_t)(n1 * R2 + n2) * inner] : make_double2(0.0, 0.0);
+  RegDft<R1, DIR>::run(v, tw, N / R1);
+#pragma unroll
+  for (int k1 = 1; k1 < R1; k1++) {
+    double2 w = tw[(n2 * k1) % N];
+    double wy = DIR * w.y;
+    double2 a = v[k1];
+    v[k1] = make_double2(__builtin_fma(a.x, w.x, -a.y * wy), __builtin_fma(a.x, wy, a.y * w.x));
+  }
+  // step 2 mapping: task (line, k1); R1 <= R2 so LPW * R1 <= threads
+  int l2, k1t;
+  if (STRIDED) {
+    l2 = tid % LPW;
+    k1t = tid / LPW;
+  } else {
+    k1t = tid % R1;
+    l2 = tid / R1;
+  }
+  const bool active2 = STRIDED ? (k1t < R1) : (l2 < LPW);
+  double2 u[R2];
+  // exchange: real plane, then imaginary plane
+#pragma unroll
+  for (int c = 0; c < 2; c++) {
+#pragma unroll
+    for (int k1 = 0; k1 < R1; k1++) plane[l1 * LS + k1 * (R2 + 1) + n2] = c ? v[k1].y : v[k1].x;
+    __syncthreads();
+    if (active2) {
+#pragma unroll
+      for (int j = 0; j < R2; j++) {
+        double x = plane[l2 * LS + k1t * (R2 + 1) + j];
+        if (c) u[j].y = x;
+        else u[j].x = x;
+      }
+    }
+    __syncthreads();
+  }
+  if (!active2) return;
+  RegDft<R2, DIR>::run(u, tw, N / R2);
+  const int64_t L2 = line0 + l2;
+  if (L2 >= nlines) return;
+  const int64_t o2 = L2 / inner, i2 = L2 % inner;
+  double2* dst = out + o2 * N * inner + i2;
+#pragma unroll
+  for (int k2 = 0; k2 < R2; k2++) {
+    double2 x = u[k2];
+    if (post_scale != 1.0) x = make_double2(x.x * post_scale, x.y * post_scale);
+    dst[(int64_t)(k1t + R1 * k2) * inner] = x;
+  }
+}
+
+template <int R1, int R2>
+static hipError_t launch_4step(const double2* in, double2* out, const NatAxis& A, int inverse, double ps,
+                               hipStream_t st) {
+  constexpr int LPW = kNatThreads / R2;
+  int64_t nlines = A.outer * A.inner;
+  int64_t grid = (nlines + LPW - 1) / LPW;
+  bool strided = A.inner > 1;
+  if (strided) {
+    if (inverse)
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, -1>), dim3((unsigned)grid), dim3(kNatThreads), 0, st,
+                         in, out, A.inner, nlines, A.tw, ps);
+    else
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, 1>), dim3((unsigned)grid), dim3(kNatThreads), 0, st,
+                         in, out, A.inner, nlines, A.tw, ps);
+  } else {
+    if (inverse)
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, false, -1>), dim3((unsigned)grid), dim3(kNatThreads), 0,
+                         st, in, out, A.inner, nlines, A.tw, ps);
+    else
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, false, 1>), dim3((unsigned)grid), dim3(kNatThreads), 0,
+                         st, in, out, A.inner, nlines, A.tw, ps);
+  }
+  return hipGetLastError();
+}
+
+// Returns hipErrorNotSupported when N has no register split.
+static hipError_t launch_native_axis(const double2* in, double2* out, const NatAxis& A, int inverse, double ps,
+                                     hipStream_t st) {
+  switch (A.N) {
+    case 1024: return launch_4step<32, 32>(in, out, A, inverse, ps, st);
+    case 512: return launch_4step<16, 32>(in, out, A, inverse, ps, st);
+    case 256: return launch_4step<16, 16>(in, out, A, inverse, ps, st);
+    case 192: return launch_4step<12, 16>(in, out, A, inverse, ps, st);
+    case 128: return launch_4step<8, 16>(in, out, A, inverse, ps, st);
+    case 96: return launch_4step<6, 16>(in, out, A, inverse, ps, st);
+    case 64: return launch_4step<8, 8>(in, out, A, inverse, ps, st);
+    case 48: return launch_4step<6, 8>(in, out, A, inverse, ps, st);
+    case 32: return launch_4step<4, 8>(in, out, A, inverse, ps, st);
+    case 24: return launch_4step<3, 8>(in, out, A, inverse, ps, st);
+    case 16: return launch_4step<4, 4>(in, out, A, inverse, ps, st);
+    case 12: return launch_4step<3, 4>(in, out, A, inverse, ps, st);
+    case 8: return launch_4step<2, 4>(in, out, A, inverse, ps, st);
+    case 4: return launch_4step<2, 2>(in, out, A, inverse, ps, st);
+    default: return hipErrorNotSupported;
+  }
+}
+
 __global__ void scale_kernel(void* data, int64_t n, double f, int tgt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -283,17 +471,33 @@ hipError_t native_execute(NativePlan* np, const void* in, void* out, void* /*ws*
   for (int k = 0; k < 3; k++) {
     int a = 2 - k;
     NatAxis A = np->ax[a];
-    int64_t nlines = A.outer * A.inner;
-    int64_t grid = (nlines + A.B - 1) / A.B;
-    size_t lds = (size_t)A.B * A.N * sizeof(double2);
     double ps = (inverse && k == 2) ? 1.0 / (double)total : 1.0;
-    if (inverse)
-      hipLaunchKernelGGL(native_axis_kernel<-1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
-                         (double2*)out, A, ps);
-    else
-      hipLaunchKernelGGL(native_axis_kernel<1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
-                         (double2*)out, A, ps);
-    hipError_t e = hipGetLastError();
+    if (A.N == 1) {
+      if (src != (const double2*)out || ps != 1.0) {
+        hipError_t e = hipMemcpyAsync(out, src, total * sizeof(double2), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        if (ps != 1.0) {
+          e = launch_scale(out, 2 * total, ps, 0, st);
+          if (e != hipSuccess) return e;
+        }
+      }
+      src = (const double2*)out;
+      continue;
+    }
+    hipError_t e = launch_native_axis(src, (double2*)out, A, inverse, ps, st);
+    if (e == hipErrorNotSupported) {
+      (void)hipGetLastError();
+      int64_t nlines = A.outer * A.inner;
+      int64_t grid = (nlines + A.B - 1) / A.B;
+      size_t lds = (size_t)A.B * A.N * sizeof(double2);
+      if (inverse)
+        hipLaunchKernelGGL(native_axis_kernel<-1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
+                           (double2*)out, A, ps);
+      else
+        hipLaunchKernelGGL(native_axis_kernel<1>, dim3((unsigned)grid), dim3(kNatThreads), lds, st, src,
+                           (double2*)out, A, ps);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     src = (const double2*)out;
   }

@@ -180,8 +180,8 @@ __device__ __forceinline__ v8h load_record(const unsigned char* rec, int h) {
 }
 
 template <int SUB, int TGT, int KMAX>
-__global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
-                                                            const CrtConsts C) {
+__device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
+                                           int64_t tile, unsigned char* smem) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
@@ -192,7 +192,6 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   constexpr int DIG = LY::DIG;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
-  extern __shared__ __align__(16) unsigned char smem[];
   const int K = P.K;
   unsigned char* dig0 = smem;
   unsigned char* dig1 = smem + DIG;
@@ -205,10 +204,10 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t g = 0, cstart;
   if (P.stage == 1) {
-    cstart = (int64_t)blockIdx.x * NCOL;
+    cstart = tile * NCOL;
   } else {
-    g = blockIdx.x / P.tiles_per_g;
-    cstart = (int64_t)(blockIdx.x % P.tiles_per_g) * NCOL;
+    g = tile / P.tiles_per_g;
+    cstart = (tile % P.tiles_per_g) * NCOL;
   }
   if (tid < NCOL) {
     int64_t c = cstart + tid;
@@ -265,6 +264,9 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
 
   const int mt = (MT == 2) ? (wave & 1) : 0;
   const int nt = (MT == 2) ? (wave >> 1) : wave;
+  // A batched launch may run a K <= 16 stage on the two-M-tile shape: the
+  // second M-tile then has no rows and no matrix planes.
+  const bool mt_active = 16 * mt < K;
   const uint8_t* amat = P.amat + g * P.amat_g_stride;
   const int col = nt * 16 + (lane & 15);
 
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
     // A-operand planes of this modulus, issued before the deconstruction so
     // that their latency overlaps it (INT8: 3 forms x 2 limbs, one chunk).
     v4i ai8[3][2];
-    if (SUB == SUB_INT8) {
+    if (SUB == SUB_INT8 && mt_active) {
 #pragma unroll
       for (int form = 0; form < 3; form++)
 #pragma unroll
@@ -307,6 +309,7 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
       }
     }
     __syncthreads();
+    if (!mt_active) continue;
     // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) ----
     float Dv[4], Ev[4], Fv[4];
     if (SUB == SUB_FP8) {
@@ -409,6 +412,35 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
       else
         op[idx] = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
     }
+  }
+}
+
+template <int SUB, int TGT, int KMAX>
+__global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
+                                                            const CrtConsts C) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_tile<SUB, TGT, KMAX>(P, MC, C, (int64_t)blockIdx.x, smem);
+}
+
+// Persistent batched stage: every workgroup walks the tiles of all
+// transforms of one Bailey pass.  descs[d] describes transform d's stage and
+// prefix[d] is the index of its first tile (prefix[ndesc] = total tiles).
+template <int SUB, int TGT, int KMAX>
+__global__ __launch_bounds__(kThreads) void ob_batch_kernel(const StageParams* __restrict__ descs,
+                                                            const int64_t* __restrict__ prefix, int ndesc,
+                                                            const ModConsts MC, const CrtConsts C) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t total = prefix[ndesc];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const StageParams P = descs[lo];
+    stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo], smem);
+    __syncthreads();
   }
 }
 
@@ -542,6 +574,32 @@ hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts&
                     : launch_stage_k<SUB_INT8, 1>(P, MC, C, grid, st);
   return tgt == 0 ? launch_stage_k<SUB_FP8, 0>(P, MC, C, grid, st)
                   : launch_stage_k<SUB_FP8, 1>(P, MC, C, grid, st);
+}
+
+template <int SUB, int KMAX>
+static hipError_t launch_batch_t(const StageParams* descs, const int64_t* prefix, int ndesc, int64_t grid,
+                                 const ModConsts& MC, const CrtConsts& C, hipStream_t st) {
+  int lds = StageLds<SUB, 0, KMAX>::bytes(KMAX);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)ob_batch_kernel<SUB, 0, KMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, descs, prefix,
+                     ndesc, MC, C);
+  return hipGetLastError();
+}
+
+// FP64-target batched pass; kmax <= 16 uses the 64-column shape, else 32.
+hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* prefix, int ndesc,
+                        int64_t grid, const ModConsts& MC, const CrtConsts& C, hipStream_t st) {
+  if (sub == SUB_INT8)
+    return kmax <= 16 ? launch_batch_t<SUB_INT8, 16>(descs, prefix, ndesc, grid, MC, C, st)
+                      : launch_batch_t<SUB_INT8, 32>(descs, prefix, ndesc, grid, MC, C, st);
+  return kmax <= 16 ? launch_batch_t<SUB_FP8, 16>(descs, prefix, ndesc, grid, MC, C, st)
+                    : launch_batch_t<SUB_FP8, 32>(descs, prefix, ndesc, grid, MC, C, st);
 }
 
 // Columns per workgroup of the stage kernel for contraction length K.

@@ -1,0 +1,139 @@
+"""The workload configurations of the method on the GPU, checked against the oracle.
+
+* 256^3, magnitudes 2^u (u uniform in [-20, 20]) with random signs and phases:
+  forward bit-exact against the exact-pipeline oracle, inverse round trip,
+  and emulated error no worse than the native FP64 FFT's (both against the
+  double-double DFT on sampled lines).
+* 1024^3 uniform[-1, 1): sampled output lines bit-exact against the oracle's
+  exact pipeline (the oracle evaluates only the cost cone of each line).
+* the differentiable spectral loss: adjoint gradient against central finite
+  differences at 16^3 and against a native-FP64 reference gradient at 512^3.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import rel_l2
+from oracle import exact as ox
+from paper_2606_23698_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _pq(plan):
+    info = plan.info()
+    return tuple(zip(info["p"], info["q"]))
+
+
+def test_wide_range_256cubed_bit_exact_and_round_trip(gpu):
+    from paper_2606_23698_amd import api
+    shape = (256, 256, 256)
+    x = inputs.wide_range(shape, 1)
+    plan = api.Plan(shape, substrate="int8")
+    xt = torch.from_numpy(x).to(gpu)
+    y = plan.forward(xt)
+    back = plan.inverse(y)
+    yn = plan.native_forward(xt)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    ref = ox.fft3_exact(x, _pq(plan))
+    assert np.count_nonzero(yh != ref) == 0
+    # round trip through the emulated inverse
+    assert rel_l2(back.cpu().numpy(), x) <= 1e-14
+    # accuracy on 8 sampled axis-0 lines of the double-double DFT of a 32^3 block
+    # is covered at small sizes; here compare emulated and native against each other
+    d = float(torch.linalg.vector_norm(y - yn) / torch.linalg.vector_norm(yn))
+    assert d <= 1e-14
+
+
+def test_wide_range_64cubed_error_against_native(gpu):
+    from paper_2606_23698_amd import api
+    shape = (64, 64, 64)
+    x = inputs.wide_range(shape, 1)
+    plan = api.Plan(shape, substrate="int8")
+    xt = torch.from_numpy(x).to(gpu)
+    y = plan.forward(xt).cpu().numpy()
+    yn = plan.native_forward(xt).cpu().numpy()
+    hi, lo = ox.fft3_dd(x)
+    e_emu, e_nat = rel_l2(y, hi, lo), rel_l2(yn, hi, lo)
+    print(f"wide-range 64^3: emulated {e_emu:.3e}, native FP64 {e_nat:.3e}")
+    assert e_emu <= 1e-14
+    # the method quantises each column to 53-bit significands relative to the
+    # column maximum and every twiddle to 53 bits; on 2^+-20 data its normwise
+    # error is within a small factor of a correctly rounded native FFT's
+    assert e_emu <= 2.0 * e_nat, (e_emu, e_nat)
+
+
+def test_1024cubed_sampled_lines_bit_exact(gpu):
+    """Eight final-axis output lines at 1024^3 against the oracle's exact pipeline.
+
+    Line (k2, k3) along axis 1 depends on every input: the oracle evaluates the
+    axis-3 output k3 of all N^2 lines, then the axis-2 output k2 of the N lines
+    (j1, ., k3), then the whole axis-1 line -- the same definitions, only where
+    the sampled outputs depend on them.
+    """
+    from paper_2606_23698_amd import api
+    N = 1024
+    shape = (N, N, N)
+    plan = api.Plan(shape, substrate="int8")
+    (p1, q1), (p2, q2), (p3, q3) = _pq(plan)
+    xt = inputs.device_uniform(shape, 2, device=gpu)
+    y = plan.forward(xt)
+    torch.cuda.synchronize()
+    samples = [(0, 5), (17, 5), (511, 5), (1023, 5), (3, 1000), (64, 1000), (700, 1000), (1000, 1000)]
+    got = {s: y[:, s[0], s[1]].cpu().numpy() for s in samples}
+    del y
+    x = xt.cpu().numpy()
+    del xt
+    torch.cuda.empty_cache()
+    for k3 in sorted({k3 for _, k3 in samples}):
+        a3 = ox.lines_at(x.reshape(-1, N), N, p3, q3, k3).reshape(N, N)   # [j1, j2]
+        for k2 in sorted({k2 for k2, kk in samples if kk == k3}):
+            a2 = ox.lines_at(a3, N, p2, q2, k2)                              # [j1]
+            a1 = ox.lines(a2.reshape(1, N), N, p1, q1)[0]
+            assert np.count_nonzero(got[(k2, k3)] != a1) == 0, (k2, k3)
+
+
+def test_spectral_loss_gradient_finite_differences(gpu):
+    from paper_2606_23698_amd import autograd as ag
+    shape = (16, 16, 16)
+    x = torch.from_numpy(inputs.uniform(shape, 4)).to(gpu).requires_grad_(True)
+    w = ag.spectral_weights(shape, gpu)
+    L = ag.spectral_loss(x, w)
+    L.backward()
+    g = x.grad.detach()
+    # analytic gradient 2 F^H (w^2 F x), in float64 with torch's FFT on the CPU
+    xc = x.detach().cpu()
+    wc = w.cpu()
+    ref = 2 * torch.fft.ifftn(wc ** 2 * torch.fft.fftn(xc), norm="forward")
+    assert float(torch.linalg.vector_norm(g.cpu() - ref) / torch.linalg.vector_norm(ref)) < 1e-13
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        d = torch.from_numpy(rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)).to(gpu)
+        eps = 1e-6
+        with torch.no_grad():
+            lp = ag.spectral_loss(x + eps * d, w)
+            lm = ag.spectral_loss(x - eps * d, w)
+        fd = float((lp - lm) / (2 * eps))
+        an = float(torch.sum((torch.conj(g) * d).real))
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9, (fd, an)
+
+
+def test_spectral_loss_gradient_512cubed_vs_native(gpu):
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd import autograd as ag
+    shape = (512, 512, 512)
+    x = inputs.device_uniform(shape, 4, device=gpu).requires_grad_(True)
+    w = ag.spectral_weights(shape, gpu)
+    L = ag.spectral_loss(x, w)
+    L.backward()
+    g = x.grad.detach()
+    del L
+    plan = api.get_plan(shape, "fp64", "auto", 0)
+    with torch.no_grad():
+        yn = plan.native_forward(x.detach())
+        yn.mul_(w * w)
+        # F^H z = conj(F conj z): native FP64 reference gradient
+        ref = torch.conj(plan.native_forward(torch.conj(yn).resolve_conj())).resolve_conj().mul_(2.0)
+        err = float(torch.linalg.vector_norm(g - ref) / torch.linalg.vector_norm(ref))
+    assert err < 1e-13, err

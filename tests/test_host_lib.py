@@ -1,0 +1,95 @@
+"""The C-ABI library on the CPU: exports, plan-time mathematics, host-side errors.
+
+No compute call runs here (there is no GPU); plan creation fails on the host
+checks (capacity budget, factorisation) before it touches a device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import constants as K
+from oracle import roots
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2606_23698_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    L.lib()
+    header = open(os.path.join(ROOT, "include", "obfft.h")).read()
+    decl = set(re.findall(r"^\s*(?:obfft_status_t|size_t|void|const char\*)\s+(\w+)\s*\(", header, re.M))
+    assert len(decl) >= 25
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert decl <= set(L.EXPORTED) | {"obfft_options_default"}
+
+
+@pytest.mark.parametrize("N", [4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 1024])
+def test_plan_roots_equal_oracle_roots(N):
+    from paper_2606_23698_amd import api
+    for bits in (52, 23):
+        assert np.array_equal(api.quantised_roots(N, bits), roots.quantised_roots(N, bits))
+
+
+@pytest.mark.parametrize("precision,mods", [("fp64", K.MODULI_FP64), ("fp32", K.MODULI_FP32)])
+def test_plan_crt_constants_equal_oracle(precision, mods):
+    from paper_2606_23698_amd import api
+    c = api.crt_constants(precision)
+    assert c["moduli"] == list(mods)
+    assert c["M"] == K.modulus_product(mods)
+    assert c["u"] == K.idempotents(mods)
+    assert c["w"] == K.lift_weights(mods)
+    assert c["S"] == K.n_slices(mods) and c["S_frac"] == K.n_frac_slices(mods)
+
+
+def test_capacity_budget_rejects_rev33():
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import ObfftError
+    with pytest.raises(ObfftError) as e:
+        api.Plan((32, 32, 32), moduli=K.MODULI_REV33)
+    assert e.value.status == 3   # OBFFT_CAPACITY_EXCEEDED
+
+
+def test_unsupported_and_invalid_sizes():
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import ObfftError
+    for shape, status in [((2, 32, 32), 2), ((1030, 32, 32), 2), ((32, 32, 66), 2)]:
+        with pytest.raises(ObfftError) as e:
+            api.Plan(shape)
+        assert e.value.status == status, shape
+    with pytest.raises(ObfftError) as e:
+        api.Plan((32, 32, 32), pq=((4, 8), (4, 8), (4, 4)))   # p*q != n
+    assert e.value.status == 1
+    with pytest.raises(ObfftError) as e:
+        api.Plan((32, 32, 32), moduli=[2039, 2039, 1024])      # not coprime
+    assert e.value.status == 1
+
+
+def test_status_strings_and_taps_layout():
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import status_string
+    assert status_string(0) == "OBFFT_SUCCESS"
+    assert status_string(3) == "OBFFT_CAPACITY_EXCEEDED"
+    lay = api.taps_layout()
+    assert lay["stride"] >= lay["R"] + lay["n_R"] + 1
+    assert lay["Z"] >= lay["P"] + 15 and lay["E"] >= lay["Z"] + 6
+
+
+def test_oracle_cone_matches_full_lines():
+    from oracle import exact as ox
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, (40, 96)) + 1j * rng.uniform(-1, 1, (40, 96))
+    full = ox.lines(x, 96, 8, 12)
+    for k in (0, 5, 95, 50):
+        assert np.array_equal(ox.lines_at(x, 96, 8, 12, k), full[:, k])
+    y = ox.fft3_exact(x.reshape(1, 40, 96)[:, :32, :], ((1, 1), (4, 8), (8, 12)))
+    assert y.shape == (1, 32, 96)
