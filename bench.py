@@ -22,6 +22,8 @@ METRIC = "ms per 1024^3 Z2Z FFT, emulated vs native FP64, HBM-roof fraction @≤
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TOPS = 39.3216       # 256 CU x 64 lane-ops/clk x 2.4 GHz
 C_EPI_MIN = 203                # the paper's integer-epilogue ledger, low end, instructions / output
+SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
+SUB_DTYPE = {0: "fp8", 1: "i8", 2: "f16"}
 
 
 def _events():
@@ -160,11 +162,11 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {0: "fp8", 1: "i8"}.get(info["substrate"], "i8"),
+        "dtype": SUB_DTYPE[info["substrate"]],
         "data": "synthetic",
         "config": {"workload": f"forward complex FP64 3-D FFT {N}x{N}x{N}, Re/Im uniform[-1,1) seed 2",
                    "n": shape, "p": info["p"], "q": info["q"], "moduli": info["r"],
-                   "substrate": {0: "fp8", 1: "int8"}.get(info["substrate"])},
+                   "substrate": SUB_NAME[info["substrate"]]},
         "native_fp64_ms": round(ms_nat, 3) if ms_nat == ms_nat else None,
         "emulated_over_native": round(ms / ms_nat, 2) if ms_nat == ms_nat else None,
         "hbm_roof_ms": round(roof_ms, 3),

@@ -63,10 +63,14 @@ enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
 
 /* MFMA substrate of the residue GEMMs.  All substrates produce bit-identical
  * outputs (the residues of an exact integer product are unique).
- *   FP8  : E4M3 digit planes, v_mfma_f32_16x16x32_fp8_fp8, FP32 accumulation
- *   INT8 : two signed 8-bit limbs, v_mfma_i32_16x16x64_i8, INT32 accumulation
- *   FP16 : one FP16 operand per residue, v_mfma_f32_16x16x16_f16
- *   AUTO : per modulus, the cheapest of the three (chosen at plan time) */
+ *   FP8  : E4M3 radix-32 digit planes, v_mfma_f32_16x16x32_fp8_fp8, FP32
+ *          accumulation, three Karatsuba products
+ *   INT8 : 8-bit limbs (radix 128), v_mfma_i32_16x16x64_i8, INT32
+ *          accumulation, three Karatsuba products
+ *   FP16 : radix-128 data limbs against whole FP16 matrix residues,
+ *          v_mfma_f32_16x16x32_f16, exact FP32 accumulation of the four real
+ *          products straight into Re and Im
+ *   AUTO : FP16 (the fewest vector instructions per output) */
 enum { OBFFT_SUB_FP8 = 0, OBFFT_SUB_INT8 = 1, OBFFT_SUB_FP16 = 2, OBFFT_SUB_AUTO = 3 };
 
 typedef struct {
@@ -172,7 +176,8 @@ void obfft_taps_layout(obfft_taps_layout_t* layout);
  * 16x16x32 MFMA (a, b: 64 x 8 bytes, d: 64 x 4 float); 1: INT8 16x16x64
  * (64 x 16 bytes, d: 64 x 4 int32); 2: FP16 32x32x16 (64 x 8 half, d: 64 x
  * 16 float); 3: permlane32 swap (a, b: 64 uint32, d: 2 x 64 uint32); 4: E4M3
- * conversion of 64 floats in a (b unused) into 64 bytes of d. */
+ * conversion of 64 floats in a (b unused) into 64 bytes of d; 5: FP16
+ * 16x16x32 (64 x 8 half, d: 64 x 4 float). */
 obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream);
 
 /* Host-only introspection (no device needed). */

@@ -1,0 +1,105 @@
+"""Autotuner: per shape, the six-step factorisation and the MFMA substrate.
+
+Candidates per axis are the admissible splits N = p q (both even, both <= 32;
+p <= q and p > q are different plans with different output bits, as the
+factorisation fixes which roundings happen where); candidates for the
+substrate are FP8 and INT8 (bit-identical outputs).  Every candidate plan is
+timed on the device with HIP events (median of `reps` forward transforms on
+a seeded input) and the fastest is cached in a JSON file keyed by shape,
+precision and device name ($OBFFT_AUTOTUNE_CACHE, default
+~/.cache/obfft/autotune.json).
+"""
+import itertools
+import json
+import os
+
+import torch
+
+from . import api, inputs
+
+MAX_K = 32
+
+
+def splits(N):
+    out = []
+    for p in range(2, MAX_K + 1, 2):
+        if N % p == 0:
+            q = N // p
+            if q % 2 == 0 and 2 <= q <= MAX_K:
+                out.append((p, q))
+    return out
+
+
+def _cache_path():
+    return os.environ.get("OBFFT_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "obfft", "autotune.json"))
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    path = _cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_plan(plan, x, reps):
+    y = torch.empty_like(x)
+    plan.forward(x, y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.forward(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(shape, precision="fp64", substrates=("int8", "fp8"), reps=3, max_candidates=16,
+         use_cache=True):
+    """Returns {"substrate", "pq", "ms"} for the fastest candidate plan of `shape`."""
+    shape = tuple(int(n) for n in shape)
+    dev = torch.cuda.get_device_name(0)
+    key = f"{shape[0]}x{shape[1]}x{shape[2]}/{precision}/{dev}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]
+    per_axis = [splits(n) for n in shape]
+    if any(not s for s in per_axis):
+        raise ValueError(f"no admissible factorisation for {shape}")
+    # keep the candidate count bounded: the splits nearest sqrt(N) first
+    per_axis = [sorted(s, key=lambda pq: abs(pq[0] - pq[1]))[:2] for s in per_axis]
+    cands = list(itertools.product(substrates, itertools.product(*per_axis)))[:max_candidates]
+    dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    x = inputs.device_uniform(shape, 0, dtype=dtype)
+    best = None
+    for sub, pq in cands:
+        plan = api.Plan(shape, precision=precision, substrate=sub, pq=pq)
+        ms = _time_plan(plan, x, reps)
+        plan.close()
+        if best is None or ms < best["ms"]:
+            best = {"substrate": sub, "pq": [list(v) for v in pq], "ms": ms}
+    if use_cache:
+        cache = _load()
+        cache[key] = best
+        _store(cache)
+    return best
+
+
+def tuned_plan(shape, precision="fp64", **kw):
+    t = tune(shape, precision, **kw)
+    return api.Plan(shape, precision=precision, substrate=t["substrate"], pq=[tuple(v) for v in t["pq"]])

@@ -14,6 +14,8 @@ def build(verbose=False, jobs=4):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # MFMA results in ordinary VGPRs: no accumulator-register copies
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
              "-Wno-unused-result", "-Wno-unused-value"]
     objdir = os.path.join(HERE, "_build")

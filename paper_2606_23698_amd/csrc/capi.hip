@@ -133,7 +133,7 @@ static obfft_status_t upload(obfft_plan_t plan, const void* host, size_t bytes, 
 static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) {
   plan->precision = opt->precision;
   int sub = opt->substrate;
-  if (sub == OBFFT_SUB_AUTO || sub == OBFFT_SUB_FP16) sub = OBFFT_SUB_INT8;
+  if (sub == OBFFT_SUB_AUTO) sub = OBFFT_SUB_FP16;
   plan->substrate = sub;
   plan->kbits = plan->precision == OBFFT_PREC_FP32 ? 24 : 53;
   const int32_t* mods = plan->precision == OBFFT_PREC_FP32 ? kModFP32 : kModFP64;
@@ -519,9 +519,9 @@ extern "C" void obfft_taps_layout(obfft_taps_layout_t* t) {
 
 // Runs one MFMA (or lane-swap / conversion) probe on device buffers; used by
 // the hardware-contract tests.  kind: 0 fp8 16x16x32, 1 i8 16x16x64,
-// 2 f16 32x32x16, 3 permlane32 swap, 4 E4M3 conversion.
+// 2 f16 32x32x16, 3 permlane32 swap, 4 E4M3 conversion, 5 f16 16x16x32.
 extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream) {
-  if (kind < 0 || kind > 4 || !a || !d || (kind < 4 && !b)) return OBFFT_INVALID_VALUE;
+  if (kind < 0 || kind > 5 || !a || !d || (kind != 4 && !b)) return OBFFT_INVALID_VALUE;
   if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
   return launch_mfma_probe(kind, a, b, d, (hipStream_t)stream) == hipSuccess ? OBFFT_SUCCESS : OBFFT_HIP_ERROR;
 }

@@ -42,6 +42,9 @@ __device__ __forceinline__ v4f mfma_fp8(long a, long b, v4f c) {
 __device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ v4f mfma_f16_16(v8h a, v8h b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 __device__ __forceinline__ v16f mfma_f16_32(v8h a, v8h b, v16f c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }

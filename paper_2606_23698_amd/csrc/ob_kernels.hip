@@ -41,23 +41,10 @@ struct Tgt<1> {
   static constexpr int PREC = 24, R = 6, S = 8, TZ = 6, NW = 3;
 };
 
-template <int SUB>
-struct SubLayout;
-template <>
-struct SubLayout<SUB_FP8> {
-  static constexpr int BPL = 8;       // operand bytes per lane per MFMA
-  static constexpr int SLOTS = 32;    // K slots per MFMA
-  static constexpr int FMAX = 3;
-};
-template <>
-struct SubLayout<SUB_INT8> {
-  static constexpr int BPL = 16;
-  static constexpr int SLOTS = 64;
-  static constexpr int FMAX = 2;
-};
-
+// K-chunks of one MFMA operand plane: INT8 64 slots (2 limbs per index),
+// FP16 32 slots (2 limbs per index), FP8 32 slots (up to 4 digits per index).
 __host__ __device__ constexpr int chunks_for(int sub, int K) {
-  return sub == SUB_INT8 ? (2 * K + 63) / 64 : (4 * K + 31) / 32;
+  return sub == SUB_INT8 ? (2 * K + 63) / 64 : sub == SUB_FP16 ? (2 * K + 31) / 32 : (4 * K + 31) / 32;
 }
 
 __host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
@@ -84,8 +71,10 @@ struct ResLayout {
   static constexpr int ROW = 32 * REC + 8;               // bytes per matrix row of a tile
 };
 
+// Data operand planes of one modulus: INT8 and FP8 three Karatsuba forms
+// (a~, b~, a~ + b~), FP16 the two forms of the four-product complex GEMM.
 __host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
-  return 3 * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_INT8 ? 16 : 8);
+  return (sub == SUB_FP16 ? 2 : 3) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
 }
 
 template <int SUB, int TGT, int KMAX>
@@ -124,17 +113,64 @@ __device__ __forceinline__ void put_digits_fp8(unsigned char* dig, int form, int
   }
 }
 
-// Two signed 8-bit limbs, v = d0 + 128 d1 with d0 in [-64, 63]; |v| <= 2043
-// gives |d1| <= 16.  The limbs are packed into one 16-bit word by v_perm.
-template <int CHB, int NT>
-__device__ __forceinline__ void put_digits_i8(unsigned char* dig, int form, int jc, int s, int v) {
-  int d1 = (v + 64) >> 7;
-  int d0 = v - (d1 << 7);
-  uint32_t wd = __builtin_amdgcn_perm((uint32_t)d1, (uint32_t)d0, 0x0c0c0400u);
-  int slot = s * 2, ch = slot >> 6, kk = slot & 63;
-  int ln = (jc & 15) + 16 * (kk >> 4);
-  int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 16 + (kk & 15);
-  *(uint16_t*)(dig + off) = (uint16_t)wd;
+// INT8 limbs of a residue v (|v| <= 2043): v = d0 + 128 d1 with the low limb
+// d0 = v mod 128 in [0, 127] and the high limb d1 = floor(v / 128) in
+// [-16, 15], both valid signed bytes.  Returns the 16-bit pair (d0 | d1 << 8).
+__device__ __forceinline__ uint32_t i8_limbs(int v) {
+  return (((uint32_t)v << 1) & 0xFF00u) | ((uint32_t)v & 0x7Fu);
+}
+
+// Byte offset of contraction index s of column jc in one form's INT8 planes
+// ([N-tile][lane][16 bytes]: lane (jc % 16) + 16 (s / 8), byte 2 (s % 8)).
+__device__ __forceinline__ int i8_slot(int jc, int s) {
+  return ((jc >> 4) * 64 + (jc & 15) + 16 * (s >> 3)) * 16 + 2 * (s & 7);
+}
+
+// Writes the limb pairs of KQ consecutive contraction indices s0.. of one
+// column and one Karatsuba form (KQ = 1, 2, 4 stay inside one lane's 16
+// bytes and take one store; KQ = 3 may cross a lane and stores per index).
+template <int KQ>
+__device__ __forceinline__ void put_limbs(unsigned char* form_base, int jc, int s0, const uint32_t* w) {
+  if (KQ == 4) {
+    *(uint2*)(form_base + i8_slot(jc, s0)) = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
+  } else if (KQ == 2) {
+    *(uint32_t*)(form_base + i8_slot(jc, s0)) = w[0] | (w[1] << 16);
+  } else {
+#pragma unroll
+    for (int u = 0; u < KQ; u++) *(uint16_t*)(form_base + i8_slot(jc, s0 + u)) = (uint16_t)w[u];
+  }
+}
+
+// FP16 limbs of a residue r (|r| <= 1022): r = d0 + 128 d1 with balanced
+// d0 = r - 128 rne(r / 128) in [-64, 64] and d1 in [-8, 8], packed as two
+// halves (d0 low).  Both are exact in FP16 (the conversion truncates, and
+// small integers need no rounding).
+__device__ __forceinline__ uint32_t f16_limbs(float r) {
+  float t = __builtin_rintf(r * 0.0078125f);
+  float d0 = __builtin_fmaf(-128.0f, t, r);
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(d0, t));
+}
+
+// Byte offset of contraction index s of column jc in one form's FP16 planes
+// ([chunk][N-tile][lane][8 halves]; slots 2s, 2s + 1 of chunk s / 16 sit in
+// lane (jc % 16) + 16 ((s % 16) / 4) at half 2 (s % 4)).
+template <int NT>
+__device__ __forceinline__ int f16_slot(int jc, int s) {
+  return ((s >> 4) * NT + (jc >> 4)) * 1024 + ((jc & 15) + 16 * ((s & 15) >> 2)) * 16 + 4 * (s & 3);
+}
+
+// Writes the packed limb pairs of KQ consecutive indices s0.. (KQ = 4 starts
+// on a multiple of 4 and KQ = 2 on an even index: one store inside one lane).
+template <int KQ, int NT>
+__device__ __forceinline__ void put_limbs16(unsigned char* form_base, int jc, int s0, const uint32_t* w) {
+  if (KQ == 4) {
+    *(uint4*)(form_base + f16_slot<NT>(jc, s0)) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if (KQ == 2) {
+    *(uint2*)(form_base + f16_slot<NT>(jc, s0)) = make_uint2(w[0], w[1]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < KQ; u++) *(uint32_t*)(form_base + f16_slot<NT>(jc, s0 + u)) = w[u];
+  }
 }
 
 // Phase A for 64 scalar outputs (two 32x32x16 FP16 MFMAs) and the swap that
@@ -143,7 +179,7 @@ template <int NV>
 __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, float* yv) {
   v16f c;
 #pragma unroll
-  for (int v = 0; v < 16; v++) c[v] = 8388608.0f;  // 2^23: the deposit bias
+  for (int v = 0; v < 16; v++) c[v] = 12582912.0f;  // 1.5 * 2^23: the deposit bias
   v16f d1 = mfma_f16_32(aop, b1, c);
   v16f d2 = mfma_f16_32(aop, b2, c);
 #pragma unroll
@@ -179,9 +215,14 @@ __device__ __forceinline__ v8h load_record(const unsigned char* rec, int h) {
   return b;
 }
 
+// Dynamic LDS of the stage and batch kernels.  Referenced directly (not
+// through a pointer argument) so that every access keeps the LDS address
+// space after inlining.
+extern __shared__ __align__(16) unsigned char smem[];
+
 template <int SUB, int TGT, int KMAX>
 __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                                           int64_t tile, unsigned char* smem) {
+                                           int64_t tile) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
@@ -193,8 +234,6 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
   const int K = P.K;
-  unsigned char* dig0 = smem;
-  unsigned char* dig1 = smem + DIG;
   unsigned char* res = smem + 2 * DIG;
   int64_t* col_in = (int64_t*)(res + LY::res_bytes(K));
   int64_t* col_out = col_in + NCOL;
@@ -269,9 +308,16 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   const bool mt_active = 16 * mt < K;
   const uint8_t* amat = P.amat + g * P.amat_g_stride;
   const int col = nt * 16 + (lane & 15);
+  // INT8 planes: [form][N-tile][lane][16 bytes]; contraction index s of
+  // column jc sits in lane (jc % 16) + 16 (s / 8) at byte 2 (s % 8).
+  constexpr int kI8FormBytes = NT * 64 * 16;
+  const int s0 = part * KQ;
+  constexpr int CH16 = chunks_for(SUB_FP16, KMAX);
+  constexpr int kF16FormBytes = CH16 * NT * 1024;
+  const int nch16 = (2 * K + 31) >> 5;
 
   for (int i = 0; i < R; i++) {
-    unsigned char* dig = (i & 1) ? dig1 : dig0;
+    unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
     const double md = (double)MC.m[i], imd = MC.inv_md[i];
     const float mf = (float)MC.m[i], imf = MC.inv_mf[i];
     const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
@@ -287,17 +333,34 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
           ai8[form][f] = *(const v4i*)(amod + (((int64_t)form * P.amat_fmax + f) * P.amat_mt + mt) *
                                                   P.amat_chmax * 1024 + lane * 16);
     }
+    // FP16: planes of Re A, Im A and -Im A, CH16 chunks of 32 slots each
+    v8h a16[3][CH16];
+    if (SUB == SUB_FP16 && mt_active) {
+#pragma unroll
+      for (int form = 0; form < 3; form++)
+#pragma unroll
+        for (int ch = 0; ch < CH16; ch++)
+          if (ch < nch16)
+            a16[form][ch] = *(const v8h*)(amod + (((int64_t)form * P.amat_mt + mt) * P.amat_chmax + ch) * 1024 +
+                                          lane * 16);
+    }
     // ---- deconstruction: residues and digit planes (Sec. 2, Eq. ozaki) ----
+    // indices past K (when KQ does not divide K) store zero limbs: the FP16
+    // planes must not see stray NaN patterns even against zero matrix slots
+    uint32_t la[KQ] = {}, lb[KQ] = {}, ls[KQ] = {};
 #pragma unroll
     for (int u = 0; u < KQ; u++) {
       int s = part * KQ + u;
       if (s < K) {
-        if (SUB == SUB_INT8) {
+        if (SUB == SUB_FP16) {
+          la[u] = f16_limbs(residue_f64(ar[u], md, imd));
+          lb[u] = f16_limbs(residue_f64(br[u], md, imd));
+        } else if (SUB == SUB_INT8) {
           int ra = (int)__builtin_fma(-md, __builtin_rint(ar[u] * imd), ar[u]);
           int rb = (int)__builtin_fma(-md, __builtin_rint(br[u] * imd), br[u]);
-          put_digits_i8<CHB, NT>(dig, 0, jc, s, ra);
-          put_digits_i8<CHB, NT>(dig, 1, jc, s, rb);
-          put_digits_i8<CHB, NT>(dig, 2, jc, s, ra + rb);
+          la[u] = i8_limbs(ra);
+          lb[u] = i8_limbs(rb);
+          ls[u] = i8_limbs(ra + rb);
         } else {
           float ra = residue_f64(ar[u], md, imd);
           float rb = residue_f64(br[u], md, imd);
@@ -307,6 +370,15 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
           put_digits_fp8<SUB, CHB, NT>(dig, 2, jc, s, rs, nd);
         }
       }
+    }
+    if (SUB == SUB_INT8 && s0 < K) {
+      put_limbs<KQ>(dig, jc, s0, la);
+      put_limbs<KQ>(dig + kI8FormBytes, jc, s0, lb);
+      put_limbs<KQ>(dig + 2 * kI8FormBytes, jc, s0, ls);
+    }
+    if (SUB == SUB_FP16 && s0 < K) {
+      put_limbs16<KQ, NT>(dig, jc, s0, la);
+      put_limbs16<KQ, NT>(dig + kF16FormBytes, jc, s0, lb);
     }
     __syncthreads();
     if (!mt_active) continue;
@@ -341,19 +413,43 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
         Ev[v] = __builtin_fmaf(1024.0f, acc[1][2][v], __builtin_fmaf(32.0f, acc[1][1][v], acc[1][0][v]));
         Fv[v] = __builtin_fmaf(1024.0f, acc[2][2][v], __builtin_fmaf(32.0f, acc[2][1][v], acc[2][0][v]));
       }
+    } else if (SUB == SUB_FP16) {
+      // four real products, accumulated exactly in FP32 (every partial sum
+      // is an integer below 2^23): R = Re A x~ - Im A y~, I = Im A x~ + Re A y~
+      v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ch = 0; ch < CH16; ch++) {
+        if (ch < nch16) {
+          v8h bx = *(const v8h*)(dig + ((ch * NT + nt) * 64 + lane) * 16);
+          v8h by = *(const v8h*)(dig + kF16FormBytes + ((ch * NT + nt) * 64 + lane) * 16);
+          accR = mfma_f16_16(a16[0][ch], bx, accR);
+          accI = mfma_f16_16(a16[1][ch], bx, accI);
+          accR = mfma_f16_16(a16[2][ch], by, accR);
+          accI = mfma_f16_16(a16[0][ch], by, accI);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        Dv[v] = accR[v];
+        Ev[v] = 0.0f;
+        Fv[v] = accI[v];
+      }
     } else {
       v4i acc[3][2];
 #pragma unroll
       for (int form = 0; form < 3; form++) {
-        v4i bop = *(const v4i*)(dig + (((form * CHB) * NT + nt) * 64 + lane) * 16);
+        v4i bop = *(const v4i*)(dig + ((form * NT + nt) * 64 + lane) * 16);
 #pragma unroll
         for (int f = 0; f < 2; f++) acc[form][f] = mfma_i8(ai8[form][f], bop, (v4i){0, 0, 0, 0});
       }
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        Dv[v] = (float)(acc[0][0][v] + (acc[0][1][v] << 7));
-        Ev[v] = (float)(acc[1][0][v] + (acc[1][1][v] << 7));
-        Fv[v] = (float)(acc[2][0][v] + (acc[2][1][v] << 7));
+        int d = acc[0][0][v] + (acc[0][1][v] << 7);
+        int e = acc[1][0][v] + (acc[1][1][v] << 7);
+        int f = acc[2][0][v] + (acc[2][1][v] << 7);
+        Dv[v] = (float)(d - e);          // R (combined in INT32, exact)
+        Ev[v] = 0.0f;
+        Fv[v] = (float)(f - d - e);      // I
       }
     }
     // ---- residue-domain combines, canonical residues to the records ----
@@ -361,8 +457,16 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
     for (int v = 0; v < 4; v++) {
       const int row = 16 * mt + 4 * (lane >> 4) + v;
       if (row < K) {
-        float rr = canonical_f32(Dv[v] - Ev[v], mf, imf);
-        float ri = canonical_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+        // centred residues of R = D - E and I = F - D - E (Alg. 1 combines);
+        // the Phase-A carrier takes them signed (|v| <= m/2 + 2)
+        float rr, ri;
+        if (SUB != SUB_FP8) {
+          rr = reduce_f32(Dv[v], mf, imf);
+          ri = reduce_f32(Fv[v], mf, imf);
+        } else {
+          rr = reduce_f32(Dv[v] - Ev[v], mf, imf);
+          ri = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+        }
         unsigned char* rrow = res + (nt * K + row) * RL::ROW;
         *(_Float16*)(rrow + (lane & 15) * RL::REC + 2 * i) = (_Float16)rr;
         *(_Float16*)(rrow + (16 + (lane & 15)) * RL::REC + 2 * i) = (_Float16)ri;
@@ -370,8 +474,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
           int64_t co = col_out[col];
           if (co >= 0) {
             int64_t el = co + (int64_t)row * P.s_out_t;
-            P.dbg_res[(el * 2) * R + i] = (uint16_t)rr;
-            P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)ri;
+            P.dbg_res[(el * 2) * R + i] = (uint16_t)(rr < 0.0f ? rr + mf : rr);
+            P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)(ri < 0.0f ? ri + mf : ri);
           }
         }
       }
@@ -418,8 +522,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
 template <int SUB, int TGT, int KMAX>
 __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
                                                             const CrtConsts C) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  stage_tile<SUB, TGT, KMAX>(P, MC, C, (int64_t)blockIdx.x, smem);
+  stage_tile<SUB, TGT, KMAX>(P, MC, C, (int64_t)blockIdx.x);
 }
 
 // Persistent batched stage: every workgroup walks the tiles of all
@@ -429,7 +532,6 @@ template <int SUB, int TGT, int KMAX>
 __global__ __launch_bounds__(kThreads) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ prefix, int ndesc,
                                                             const ModConsts MC, const CrtConsts C) {
-  extern __shared__ __align__(16) unsigned char smem[];
   const int64_t total = prefix[ndesc];
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
     int lo = 0, hi = ndesc - 1;
@@ -438,8 +540,9 @@ __global__ __launch_bounds__(kThreads) void ob_batch_kernel(const StageParams* _
       if (prefix[mid] <= t) lo = mid;
       else hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads become scalar
     const StageParams P = descs[lo];
-    stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo], smem);
+    stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo]);
     __syncthreads();
   }
 }
@@ -482,8 +585,8 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
       ((float*)out)[o] = pack_f32<TT::NW>(Rw, ex);
     if (taps) {
       uint32_t* tp = taps + o * kTapStride;
-      for (int s = 0; s < TT::S; s++) tp[s] = EP::pbits(xv, yv, s) - 0x4B000000u;
-      for (int t = 0; t < TT::TZ; t++) tp[16 + t] = EP::zbits(xv, yv, t) - 0x4B000000u;
+      for (int s = 0; s < TT::S; s++) tp[s] = EP::pbits(xv, yv, s) - 0x4B400000u;
+      for (int t = 0; t < TT::TZ; t++) tp[16 + t] = EP::zbits(xv, yv, t) - 0x4B400000u;
       // E = E_b - Bp (mod 2^160)
       uint32_t E[5], bw = 0;
       for (int i = 0; i < 5; i++) {
@@ -491,7 +594,7 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
         E[i] = subc(wi, C.Bp5[i], bw, &bw);
       }
       for (int i = 0; i < 5; i++) tp[24 + i] = E[i];
-      tp[29] = zh;
+      tp[29] = zh - C.zoff;
       for (int i = 0; i < 4; i++) tp[30 + i] = i < TT::NW ? Rw[i] : (uint32_t)((int32_t)Rw[TT::NW - 1] >> 31);
       tp[34] = (uint32_t)ex;
     }
@@ -531,6 +634,10 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
     auto pr = __builtin_amdgcn_permlane32_swap(x, y, false, false);
     ((uint32_t*)d)[lane] = pr[0];
     ((uint32_t*)d)[64 + lane] = pr[1];
+  } else if (kind == 5) {
+    v8h av = ((const v8h*)a)[lane], bv = ((const v8h*)b)[lane];
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    ((v4f*)d)[lane] = mfma_f16_16(av, bv, c);
   } else if (kind == 4) {
     // E4M3 conversion of small integers: a = 64 floats, d = 64 bytes
     float x = ((const float*)a)[lane];
@@ -569,6 +676,9 @@ static hipError_t launch_stage_k(const StageParams& P, const ModConsts& MC, cons
 
 hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
                         int64_t grid, hipStream_t st) {
+  if (sub == SUB_FP16)
+    return tgt == 0 ? launch_stage_k<SUB_FP16, 0>(P, MC, C, grid, st)
+                    : launch_stage_k<SUB_FP16, 1>(P, MC, C, grid, st);
   if (sub == SUB_INT8)
     return tgt == 0 ? launch_stage_k<SUB_INT8, 0>(P, MC, C, grid, st)
                     : launch_stage_k<SUB_INT8, 1>(P, MC, C, grid, st);
@@ -595,6 +705,9 @@ static hipError_t launch_batch_t(const StageParams* descs, const int64_t* prefix
 // FP64-target batched pass; kmax <= 16 uses the 64-column shape, else 32.
 hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* prefix, int ndesc,
                         int64_t grid, const ModConsts& MC, const CrtConsts& C, hipStream_t st) {
+  if (sub == SUB_FP16)
+    return kmax <= 16 ? launch_batch_t<SUB_FP16, 16>(descs, prefix, ndesc, grid, MC, C, st)
+                      : launch_batch_t<SUB_FP16, 32>(descs, prefix, ndesc, grid, MC, C, st);
   if (sub == SUB_INT8)
     return kmax <= 16 ? launch_batch_t<SUB_INT8, 16>(descs, prefix, ndesc, grid, MC, C, st)
                       : launch_batch_t<SUB_INT8, 32>(descs, prefix, ndesc, grid, MC, C, st);

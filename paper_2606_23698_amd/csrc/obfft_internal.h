@@ -20,8 +20,9 @@ struct CrtConsts {
   int nwords;            // 32-bit words of the lift arithmetic (4: FP64 set, 3: FP32 set)
   uint32_t M[4];         // M, little-endian words
   uint32_t Mhalf[4];     // M / 2
-  uint32_t K0[4];        // (M/2 - Bp) mod 2^(32 nwords); Bp = implicit bias of the deposits
-  uint64_t Czh;          // (2^47 - Bz) mod 2^64; Bz = implicit bias of the lift bytes
+  uint32_t K0[4];        // (M/2 - Bp + zoff M) mod 2^128; Bp = implicit bias of the deposits
+  uint64_t Czh;          // (2^47 - Bz + zoff 2^48) mod 2^64; Bz = implicit bias of the lift bytes
+  uint32_t zoff;         // multiple of M added to E so that zhat stays unsigned
   uint32_t Bp5[5];       // Bp mod 2^160 (debug taps only)
 };
 

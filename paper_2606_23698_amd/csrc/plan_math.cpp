@@ -114,18 +114,31 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
     C.M[i] = (uint32_t)(M >> (32 * i));
     C.Mhalf[i] = (uint32_t)(Mh >> (32 * i));
   }
-  // Each Phase-A partial leaves the MFMA as an FP32 value 2^23 + P (the
-  // accumulator starts at 2^23), whose bit pattern is 0x4B000000 + P.  The
-  // deposits therefore carry an implicit bias Bp = sum_s 0x4B000000 256^s.
+  // Each Phase-A partial leaves the MFMA as the FP32 value 1.5 * 2^23 + P
+  // (the accumulator is seeded there; |P| < 2^22 holds for centred as well
+  // as canonical residues), whose bit pattern is 0x4B400000 + P.  The
+  // deposits therefore carry the implicit bias Bp = sum_s 0x4B400000 256^s
+  // and the lift bytes Bz = sum_t 0x4B400000 256^t.  Adding kLiftOffset M to
+  // E (and kLiftOffset 2^48 to the lift sum) keeps zhat unsigned for signed
+  // residues without changing R.
   uint32_t Bp[5] = {0, 0, 0, 0, 0};
   for (int s = 0; s < H.S; s++) add_shifted(Bp, 5, kFloatBiasBits, 8 * s);
   memcpy(C.Bp5, Bp, sizeof(Bp));
   uint32_t K0[5] = {C.Mhalf[0], C.Mhalf[1], C.Mhalf[2], C.Mhalf[3], 0};
   sub_words(K0, Bp, 5);
+  u128 cm = H.M * (u128)kLiftOffset;
+  uint32_t CM[5] = {(uint32_t)cm, (uint32_t)(cm >> 32), (uint32_t)(cm >> 64), (uint32_t)(cm >> 96), 0};
+  uint64_t carry = 0;
+  for (int i = 0; i < 5; i++) {
+    uint64_t t = (uint64_t)K0[i] + CM[i] + carry;
+    K0[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
   for (int i = 0; i < 4; i++) C.K0[i] = K0[i];
   uint64_t Bz = 0;
   for (int t = 0; t < H.T; t++) Bz += (uint64_t)kFloatBiasBits << (8 * t);
-  C.Czh = ((uint64_t)1 << (kFracBits - 1)) - Bz;
+  C.Czh = ((uint64_t)1 << (kFracBits - 1)) - Bz + ((uint64_t)kLiftOffset << kFracBits);
+  C.zoff = kLiftOffset;
 }
 
 // ---- double-double trigonometry ----
@@ -293,6 +306,7 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
   int MT = (K + 15) / 16;
   int bpl, fmax, chmax;
   if (substrate == SUB_INT8) { bpl = 16; fmax = 2; chmax = (2 * K + 63) / 64; }
+  else if (substrate == SUB_FP16) { bpl = 16; fmax = 1; chmax = (2 * K + 31) / 32; }
   else { bpl = 8; fmax = 3; chmax = (4 * K + 31) / 32; }
   int64_t chunk_bytes = 64 * bpl;
   L.fmax = fmax; L.chmax = chmax; L.mt = MT; L.G = G;
@@ -309,8 +323,35 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
           matrix_entry(roots, N, p, q, stage, g, t, s, direction, &c, &sn);
           cval[(0 * K + t) * K + s] = centred(c, m);
           cval[(1 * K + t) * K + s] = centred(sn, m);
-          cval[(2 * K + t) * K + s] = centred(c + sn, m);
+          // Karatsuba (FP8, INT8): Re A, Im A, Re A + Im A; FP16 (four
+          // products): Re A, Im A, -Im A
+          cval[(2 * K + t) * K + s] = substrate == SUB_FP16 ? centred(-sn, m) : centred(c + sn, m);
         }
+      if (substrate == SUB_FP16) {
+        // [form][M-tile][chunk][lane][8 halves]; slot 32 ch + 8 (lane / 16) + j
+        // holds limb weight 128^(slot % 2) of index slot / 2, folded mod m.
+        int pw128 = 128 % m;
+        for (int form = 0; form < 3; form++)
+          for (int mt = 0; mt < MT; mt++)
+            for (int ch = 0; ch < chmax; ch++)
+              for (int lane = 0; lane < 64; lane++)
+                for (int j = 0; j < 8; j++) {
+                  int t = 16 * mt + lane % 16;
+                  int slot = 32 * ch + 8 * (lane / 16) + j;
+                  int s = slot / 2, e = slot % 2;
+                  int val = 0;
+                  if (t < K && s < K) {
+                    int a = cval[(form * K + t) * K + s];
+                    val = e ? centred((int64_t)a * pw128, m) : a;
+                  }
+                  uint16_t h = f16_encode_int(val);
+                  int64_t off = g * L.g_stride + i * L.mod_stride +
+                                (((int64_t)form * MT + mt) * chmax + ch) * chunk_bytes + lane * bpl + 2 * j;
+                  bytes[off] = (uint8_t)(h & 0xFF);
+                  bytes[off + 1] = (uint8_t)(h >> 8);
+                }
+        continue;
+      }
       int R = substrate == SUB_INT8 ? 128 : 32;
       int nd = substrate == SUB_INT8 ? 2 : fp8_digits(m);
       int ndp = substrate == SUB_INT8 ? 2 : (nd == 3 ? 4 : 2);

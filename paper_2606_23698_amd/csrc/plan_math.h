@@ -13,7 +13,8 @@ namespace obfft {
 typedef unsigned __int128 u128;
 
 constexpr int kFracBits = 48;                  // f of the fractional lift (Sec. 5.1)
-constexpr uint32_t kFloatBiasBits = 0x4B000000u; // bit pattern of 2^23 as FP32
+constexpr uint32_t kFloatBiasBits = 0x4B400000u; // bit pattern of 1.5 * 2^23 as FP32
+constexpr uint32_t kLiftOffset = 16384;          // > max |zhat| for centred residues (12,252)
 constexpr int kFp8TwoDigitMax = 1052;          // moduli up to here need 2 radix-32 digits
 
 struct ModSet {

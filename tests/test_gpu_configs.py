@@ -29,7 +29,7 @@ def test_wide_range_256cubed_bit_exact_and_round_trip(gpu):
     from paper_2606_23698_amd import api
     shape = (256, 256, 256)
     x = inputs.wide_range(shape, 1)
-    plan = api.Plan(shape, substrate="int8")
+    plan = api.Plan(shape)
     xt = torch.from_numpy(x).to(gpu)
     y = plan.forward(xt)
     back = plan.inverse(y)
@@ -75,7 +75,7 @@ def test_1024cubed_sampled_lines_bit_exact(gpu):
     from paper_2606_23698_amd import api
     N = 1024
     shape = (N, N, N)
-    plan = api.Plan(shape, substrate="int8")
+    plan = api.Plan(shape)
     (p1, q1), (p2, q2), (p3, q3) = _pq(plan)
     xt = inputs.device_uniform(shape, 2, device=gpu)
     y = plan.forward(xt)

@@ -101,6 +101,37 @@ def test_f16_mfma_32x32x16_layout_and_exactness(gpu, extreme):
     assert np.array_equal(got, A @ B)
 
 
+@pytest.mark.parametrize("extreme", [False, True])
+def test_f16_mfma_16x16x32_layout_and_exactness(gpu, extreme):
+    """Residue-GEMM contract of the FP16 substrate: matrix residues |a| <= 1019
+    against radix-128 limbs (|d0| <= 64, |d1| <= 8), 32-term sums below 2^23."""
+    api = _api()
+    rng = np.random.default_rng(14)
+    A = rng.integers(-1019, 1020, size=(16, 32))
+    B = np.where(np.arange(32)[:, None] % 2 == 0, rng.integers(-64, 65, size=(32, 16)),
+                 rng.integers(-8, 9, size=(32, 16)))
+    if extreme:
+        A[:] = 1019
+        B[0::2] = 64
+        B[1::2] = 8
+    a = np.zeros((64, 8), np.float16)
+    b = np.zeros((64, 8), np.float16)
+    for l in range(64):
+        for j in range(8):
+            k = 8 * (l // 16) + j
+            a[l, j] = A[l % 16, k]
+            b[l, j] = B[k, l % 16]
+    d = torch.zeros((64, 4), dtype=torch.float32, device=gpu)
+    api.mfma_probe(5, torch.from_numpy(a.view(np.int16)).to(gpu), torch.from_numpy(b.view(np.int16)).to(gpu), d)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    got = np.zeros((16, 16), np.int64)
+    for l in range(64):
+        for v in range(4):
+            got[4 * (l // 16) + v, l % 16] = D[l, v]
+    assert np.array_equal(got, A @ B)
+
+
 def test_permlane32_swap_semantics(gpu):
     api = _api()
     x = torch.arange(64, dtype=torch.int32, device=gpu)

@@ -34,7 +34,7 @@ def _pq(plan):
     return tuple(zip(info["p"], info["q"]))
 
 
-@pytest.mark.parametrize("substrate", ["fp8", "int8"])
+@pytest.mark.parametrize("substrate", ["fp8", "int8", "fp16"])
 def test_forward_32cubed_bit_exact(gpu, substrate):
     api = _api()
     x = inputs.uniform((32, 32, 32), 0)
@@ -54,22 +54,24 @@ def test_forward_32cubed_bit_exact(gpu, substrate):
     ((4, 64, 24), None),
     ((32, 16, 64), ((8, 4), (4, 4), (8, 8))),
 ])
-def test_forward_small_shapes_bit_exact(gpu, shape, pq):
+@pytest.mark.parametrize("substrate", ["fp8", "fp16"])
+def test_forward_small_shapes_bit_exact(gpu, shape, pq, substrate):
     api = _api()
     x = inputs.uniform(shape, 7)
-    plan = api.Plan(shape, substrate="fp8", pq=pq)
+    plan = api.Plan(shape, substrate=substrate, pq=pq)
     y = _run(plan, x, gpu)
     ref = ox.fft3_exact(x, _pq(plan))
     assert np.count_nonzero(y != ref) == 0
 
 
-def test_stage_residue_tap_matches_oracle_integers(gpu):
+@pytest.mark.parametrize("substrate", ["fp8", "fp16"])
+def test_stage_residue_tap_matches_oracle_integers(gpu, substrate):
     """The canonical residues R_i, I_i of every stage output equal (exact integer) mod m_i."""
     api = _api()
     from oracle import constants as K
     shape = (4, 4, 32)
     x = inputs.uniform(shape, 3)
-    plan = api.Plan(shape, substrate="fp8")
+    plan = api.Plan(shape, substrate=substrate)
     p, q = plan.info()["p"][2], plan.info()["q"][2]
     xt = torch.from_numpy(x).to(gpu)
     r = 12
@@ -100,7 +102,7 @@ def test_inverse_and_adjoint(gpu):
     api = _api()
     shape = (16, 32, 8)
     x = inputs.uniform(shape, 9)
-    plan = api.Plan(shape, substrate="int8")
+    plan = api.Plan(shape)
     pq = _pq(plan)
     xinv = _run(plan, x, gpu, "inverse")
     ref = ox.fft3_exact(x, pq, inverse=True, final_shift=-12)
@@ -115,11 +117,12 @@ def test_inverse_and_adjoint(gpu):
     assert rel_l2(back, x) <= 1e-14
 
 
-def test_fp32_target_bit_exact(gpu):
+@pytest.mark.parametrize("substrate", ["fp8", "fp16"])
+def test_fp32_target_bit_exact(gpu, substrate):
     api = _api()
     shape = (16, 32, 32)
     x = inputs.uniform(shape, 4).astype(np.complex64)
-    plan = api.Plan(shape, precision="fp32", substrate="fp8")
+    plan = api.Plan(shape, precision="fp32", substrate=substrate)
     y = _run(plan, x, gpu)
     ref = ox.fft3_exact(x, _pq(plan), precision=1)
     assert y.dtype == np.complex64
