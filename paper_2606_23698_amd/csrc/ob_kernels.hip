@@ -11,17 +11,21 @@
 // Alg. 2).  The only FP64 arithmetic is the exponent/scale extraction and
 // quantisation at the start and the single rounding at the end.
 //
-// Work decomposition: a workgroup of 4 waves owns 64 contraction columns.
-// All columns of a workgroup share one stage matrix (stage 2: the same k2, so
-// the same twiddle-fused F_p^(k2), Sec. 4.1).  Per modulus:
-//   decon   every thread reduces K/4 elements of one column and writes their
-//           digit planes to LDS in the MFMA B-operand layout;
+// Work decomposition: a workgroup of 4 waves owns 32 (K > 16) or 64
+// contraction columns.  All columns of a workgroup share one stage matrix
+// (stage 2: the same k2, so the same twiddle-fused F_p^(k2), Sec. 4.1).  Per
+// modulus:
+//   decon   every thread reduces K/TPC elements of one column and writes
+//           their digit planes to LDS in the MFMA B-operand layout;
 //   GEMM    each wave multiplies its 16-row M-tile of the matrix planes (held
-//           in registers) with 16-column N-tiles from LDS;
-//   combine canonical residues of R and I go to an LDS array [output][m_i].
-// After the last modulus every wave runs Phase A on batches of 64 scalar
-// outputs (two 32x32x16 FP16 MFMAs plus one cross-half lane swap) and the
-// integer epilogue, one output per lane, and stores coalesced FP64 results.
+//           in registers) with its 16-column N-tile from LDS;
+//   combine the centred residues of R and I of the wave's 16 x 16 outputs
+//           are packed as FP16 into registers: every lane keeps the residue
+//           record of its own 8 outputs (4 rows x Re/Im) over all moduli.
+// After the last modulus every lane reconstructs its own outputs: Phase A
+// runs on 64 outputs at a time (two 32x32x16 FP16 MFMAs fed by a cross-half
+// lane swap of the records, then one swap of the partials back), followed by
+// the integer epilogue and one coalesced 16-byte store per complex output.
 #include "ob_device.h"
 
 namespace obfft {
@@ -62,28 +66,30 @@ struct Shape {
   static constexpr int KQ = (KMAX + TPC - 1) / TPC;     // elements per thread
 };
 
-// Residue records: R fp16 residues per scalar output, 32 records per matrix
-// row (16 columns x Re/Im) plus an 8-byte pad that staggers the LDS banks
-// of neighbouring rows.
-template <int R>
-struct ResLayout {
-  static constexpr int REC = 2 * R;                      // bytes per output
-  static constexpr int ROW = 32 * REC + 8;               // bytes per matrix row of a tile
-};
-
 // Data operand planes of one modulus: INT8 and FP8 three Karatsuba forms
 // (a~, b~, a~ + b~), FP16 the two forms of the four-product complex GEMM.
 __host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
   return (sub == SUB_FP16 ? 2 : 3) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
 }
 
+// LDS of one workgroup: two digit buffers (even / odd moduli), the column
+// input and output offsets, the column exponents and the per-thread partial
+// exponents.
 template <int SUB, int TGT, int KMAX>
 struct StageLds {
   typedef Shape<KMAX> SH;
-  static constexpr int R = TGT == 0 ? 12 : 6;
   static constexpr int DIG = dig_bytes(SUB, KMAX, SH::NT);
-  __host__ __device__ static int res_bytes(int K) { return align16(SH::NT * K * ResLayout<R>::ROW); }
-  __host__ __device__ static int bytes(int K) { return 2 * DIG + res_bytes(K) + SH::NCOL * 20 + kThreads * 4; }
+  __host__ __device__ static int bytes(int) { return 2 * DIG + SH::NCOL * 20 + kThreads * 4; }
+};
+
+// Split of a residue record between the two lane halves of the Phase-A
+// MFMA: the B operand of lane half h holds moduli ML h .. ML h + ML - 1 in
+// its first ML slots (ML = 6 for r = 12, 4 for r = 6), zeros after.
+template <int R>
+struct RecSplit {
+  static constexpr int RV = R / 2;              // packed FP16 pairs per output
+  static constexpr int RH = (RV + 1) / 2;       // pairs supplied by the low half
+  static constexpr int ML = 2 * RH;             // moduli per lane half
 };
 
 // Writes the digit planes of residue v (exact small integer) of column jc,
@@ -174,14 +180,13 @@ __device__ __forceinline__ void put_limbs16(unsigned char* form_base, int jc, in
 }
 
 // Phase A for 64 scalar outputs (two 32x32x16 FP16 MFMAs) and the swap that
-// gives every lane all partials of its own output.
+// gives every lane all partials of one output: lane l < 32 gets column l of
+// b1's product, lane l >= 32 column l - 32 of b2's.  `seed` is the
+// accumulator start 1.5 * 2^23 (the deposit bias), kept in VGPRs.
 template <int NV>
-__device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, float* yv) {
-  v16f c;
-#pragma unroll
-  for (int v = 0; v < 16; v++) c[v] = 12582912.0f;  // 1.5 * 2^23: the deposit bias
-  v16f d1 = mfma_f16_32(aop, b1, c);
-  v16f d2 = mfma_f16_32(aop, b2, c);
+__device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, const v16f& seed, float* xv, float* yv) {
+  v16f d1 = mfma_f16_32(aop, b1, seed);
+  v16f d2 = mfma_f16_32(aop, b2, seed);
 #pragma unroll
   for (int v = 0; v < NV; v++) {
     auto pr = __builtin_amdgcn_permlane32_swap(__float_as_uint(d1[v]), __float_as_uint(d2[v]),
@@ -191,28 +196,14 @@ __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, float* xv, floa
   }
 }
 
-// Phase-A B operand of one lane from a residue record in LDS: moduli
-// 8h .. 8h+7 of the record (zeros beyond r).
-template <int R>
-__device__ __forceinline__ v8h load_record(const unsigned char* rec, int h) {
-  v8h b;
-  if (R == 12) {
-    if (h == 0) {
-      uint2 lo = *(const uint2*)rec;
-      uint2 hi = *(const uint2*)(rec + 8);
-      uint4 w = make_uint4(lo.x, lo.y, hi.x, hi.y);
-      b = __builtin_bit_cast(v8h, w);
-    } else {
-      uint2 lo = *(const uint2*)(rec + 16);
-      uint4 w = make_uint4(lo.x, lo.y, 0u, 0u);
-      b = __builtin_bit_cast(v8h, w);
-    }
-  } else {
-    uint32_t a0 = *(const uint32_t*)rec, a1 = *(const uint32_t*)(rec + 4), a2 = *(const uint32_t*)(rec + 8);
-    uint4 w = h == 0 ? make_uint4(a0, a1, a2, 0u) : make_uint4(0u, 0u, 0u, 0u);
-    b = __builtin_bit_cast(v8h, w);
-  }
-  return b;
+__device__ __forceinline__ v16f phase_a_seed() {
+  v16f c;
+#pragma unroll
+  for (int v = 0; v < 16; v++) c[v] = 12582912.0f;  // 1.5 * 2^23
+  // opaque to the optimiser: the seed stays resident in 16 VGPRs instead of
+  // being rematerialised before every MFMA
+  asm volatile("" : "+v"(c));
+  return c;
 }
 
 // Dynamic LDS of the stage and batch kernels.  Referenced directly (not
@@ -226,7 +217,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
-  typedef ResLayout<TT::R> RL;
+  typedef RecSplit<TT::R> RS;
   constexpr int R = TT::R;
   constexpr int MT = SH::MT, NT = SH::NT, NCOL = SH::NCOL, TPC = SH::TPC, KQ = SH::KQ;
   constexpr int CHB = chunks_for(SUB, KMAX);
@@ -234,8 +225,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
   const int K = P.K;
-  unsigned char* res = smem + 2 * DIG;
-  int64_t* col_in = (int64_t*)(res + LY::res_bytes(K));
+  int64_t* col_in = (int64_t*)(smem + 2 * DIG);
   int64_t* col_out = col_in + NCOL;
   int* cexp = (int*)(col_out + NCOL);
   int* pexp = cexp + NCOL;
@@ -316,6 +306,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   constexpr int kF16FormBytes = CH16 * NT * 1024;
   const int nch16 = (2 * K + 31) >> 5;
 
+  // residue records of this lane's outputs (row 16 mt + 4 (lane / 16) + v,
+  // column col, Re / Im): rec[2 v + Re/Im][i / 2], half i % 2 = modulus i
+  v2h rec[8][RS::RV];
+#pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
     const double md = (double)MC.m[i], imd = MC.inv_md[i];
@@ -456,9 +450,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
 #pragma unroll
     for (int v = 0; v < 4; v++) {
       const int row = 16 * mt + 4 * (lane >> 4) + v;
-      if (row < K) {
-        // centred residues of R = D - E and I = F - D - E (Alg. 1 combines);
-        // the Phase-A carrier takes them signed (|v| <= m/2 + 2)
+      {
+        // centred residues of R and I (Alg. 1 combines); the Phase-A
+        // carrier takes them signed (|v| <= m/2 + 2).  Rows past K hold
+        // zero products and are never stored.
         float rr, ri;
         if (SUB != SUB_FP8) {
           rr = reduce_f32(Dv[v], mf, imf);
@@ -467,10 +462,9 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
           rr = reduce_f32(Dv[v] - Ev[v], mf, imf);
           ri = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
         }
-        unsigned char* rrow = res + (nt * K + row) * RL::ROW;
-        *(_Float16*)(rrow + (lane & 15) * RL::REC + 2 * i) = (_Float16)rr;
-        *(_Float16*)(rrow + (16 + (lane & 15)) * RL::REC + 2 * i) = (_Float16)ri;
-        if (P.dbg_res) {
+        rec[2 * v][i >> 1][i & 1] = (_Float16)rr;
+        rec[2 * v + 1][i >> 1][i & 1] = (_Float16)ri;
+        if (P.dbg_res && row < K) {
           int64_t co = col_out[col];
           if (co >= 0) {
             int64_t el = co + (int64_t)row * P.s_out_t;
@@ -481,40 +475,55 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
       }
     }
   }
-  __syncthreads();
+  if (!mt_active) return;
 
   // ---- Phase A (FP16 MFMA) + Phase B (Kulisch, lift, pack) ----
-  // Batch b = (N-tile, row pair); lane o of the batch owns output
-  // (row 2rp + o/32, column (o/2) % 16, Re/Im o % 2).
-  v8h aop = *(const v8h*)(P.phaseA + lane * 8);
-  const int h = lane >> 5;
-  const int nbatch = NT * K / 2;
-  const int o = lane & 31;
-  const int ocol = o >> 1, oprt = o & 1;
-  for (int b = wave; b < nbatch; b += 4) {
-    const int bt = b / (K / 2), rp = b % (K / 2);
-    const unsigned char* r1 = res + (bt * K + 2 * rp) * RL::ROW + (oprt * 16 + ocol) * RL::REC;
-    v8h b1 = load_record<R>(r1, h);
-    v8h b2 = load_record<R>(r1 + RL::ROW, h);
+  // Round (v, Re/Im): every lane reconstructs its own output of that row and
+  // part.  The low lane half feeds moduli 0 .. ML-1 of its record and the
+  // high half moduli ML .. r-1; one swap per packed pair hands each half the
+  // other half's share (b1: the low lanes' outputs, b2: the high lanes').
+  const v8h aop = *(const v8h*)(P.phaseA + lane * 8);
+  const v16f seed = phase_a_seed();
+  const int64_t co = col_out[col];
+  const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
+  typename TT::T re_part = 0;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int v = j >> 1, prt = j & 1;
+    if (16 * mt + v >= K) break;  // no lane of the wave has this row
+    uint32_t b1w[4] = {0u, 0u, 0u, 0u}, b2w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < RS::RH; k++) {
+      uint32_t x = __builtin_bit_cast(uint32_t, rec[j][k]);
+      uint32_t y = RS::RH + k < RS::RV ? __builtin_bit_cast(uint32_t, rec[j][RS::RH + k]) : 0u;
+      auto pr = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+      b1w[k] = pr[0];
+      b2w[k] = pr[1];
+    }
+    v8h b1 = __builtin_bit_cast(v8h, make_uint4(b1w[0], b1w[1], b1w[2], b1w[3]));
+    v8h b2 = __builtin_bit_cast(v8h, make_uint4(b2w[0], b2w[1], b2w[2], b2w[3]));
     float xv[EP::NV], yv[EP::NV];
-    phase_a<EP::NV>(aop, b1, b2, xv, yv);
+    phase_a<EP::NV>(aop, b1, b2, seed, xv, yv);
     uint32_t wv[(TT::S + 3) / 4 + 1];
     EP::deposits(xv, yv, wv, &wv[(TT::S + 3) / 4]);
     uint32_t zh = EP::zhat(xv, yv, C.Czh);
     uint32_t Rw[TT::NW];
     EP::lift(wv, zh, C, Rw);
-    const int row = 2 * rp + (lane >> 5);
-    const int c = bt * 16 + ((lane >> 1) & 15);
-    const int prt = lane & 1;
-    const int64_t co = col_out[c];
-    if (co >= 0 && row < K) {
-      const int ex = cexp[c] - 2 * (TT::PREC - 1) + P.extra_shift;
-      typename TT::T* op = (typename TT::T*)P.out;
-      int64_t idx = (co + (int64_t)row * P.s_out_t) * 2 + prt;
-      if (TGT == 0)
-        op[idx] = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
-      else
-        op[idx] = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
+    typename TT::T y;
+    if (TGT == 0)
+      y = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
+    else
+      y = (typename TT::T)pack_f32<TT::NW>(Rw, ex);
+    if (prt == 0) {
+      re_part = y;
+    } else {
+      const int row = 16 * mt + 4 * (lane >> 4) + v;
+      if (co >= 0 && row < K) {
+        typename TT::T2 z;
+        z.x = re_part;
+        z.y = y;
+        ((typename TT::T2*)P.out)[co + (int64_t)row * P.s_out_t] = z;
+      }
     }
   }
 }
@@ -559,17 +568,19 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
   const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64;
   if (base >= n) return;
   const int h = lane >> 5;
+  constexpr int ML = RecSplit<R>::ML;
   v8h aop = *(const v8h*)(phaseA + lane * 8);
   v8h b1, b2;
   const int64_t o1 = base + (lane & 31), o2 = o1 + 32;
 #pragma unroll
   for (int j = 0; j < 8; j++) {
-    int k = 8 * h + j;
-    b1[j] = (k < R && o1 < n) ? (_Float16)(float)residues[o1 * R + k] : (_Float16)0.0f;
-    b2[j] = (k < R && o2 < n) ? (_Float16)(float)residues[o2 * R + k] : (_Float16)0.0f;
+    int k = ML * h + j;  // the Phase-A operand's modulus of slot 8 h + j
+    bool use = j < ML && k < R;
+    b1[j] = (use && o1 < n) ? (_Float16)(float)residues[o1 * R + k] : (_Float16)0.0f;
+    b2[j] = (use && o2 < n) ? (_Float16)(float)residues[o2 * R + k] : (_Float16)0.0f;
   }
   float xv[EP::NV], yv[EP::NV];
-  phase_a<EP::NV>(aop, b1, b2, xv, yv);
+  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(), xv, yv);
   constexpr int NC = (TT::S + 3) / 4;
   uint32_t wv[NC + 1];
   EP::deposits(xv, yv, wv, &wv[NC]);

@@ -387,21 +387,24 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
   }
 }
 
-// Phase-A operand of v_mfma_f32_32x32x16_f16: A[row][k], row = partial
-// placement, k = modulus.  Lane l holds row l % 32, k = 8 (l / 32) + j.
-// Row rho is read back in register v = (rho % 4) + 4 (rho / 8) of lane half
-// (rho / 4) % 2; register pair v carries P_{2v}, P_{2v+1} for v < ceil(S/2)
-// and then the lift bytes Z_{2u}, Z_{2u+1}.
+// Phase-A operand of v_mfma_f32_32x32x16_f16: A[row][slot], row = partial
+// placement, slot = modulus.  Lane l holds row l % 32, slots 8 (l / 32) + j;
+// slot 8 h + j carries modulus ML h + j for j < ML (ML = 2 ceil(r / 4): 6 for
+// r = 12, 4 for r = 6), so that each lane half takes one share of a residue
+// record.  Row rho is read back in register v = (rho % 4) + 4 (rho / 8) of
+// lane half (rho / 4) % 2; register pair v carries P_{2v}, P_{2v+1} for
+// v < ceil(S/2) and then the lift bytes Z_{2u}, Z_{2u+1}.
 void build_phaseA_operand(const ModSet& H, std::vector<uint16_t>& out, int* npairs) {
   out.assign(64 * 8, 0);
   int vp = (H.S + 1) / 2, vz = (H.T + 1) / 2;
+  int ML = 2 * ((H.r / 2 + 1) / 2);
   *npairs = vp + vz;
   for (int lane = 0; lane < 64; lane++)
     for (int j = 0; j < 8; j++) {
-      int rho = lane % 32, k = 8 * (lane / 32) + j;
+      int rho = lane % 32, k = ML * (lane / 32) + j;
       int v = (rho % 4) + 4 * (rho / 8), half = (rho / 4) % 2;
       int val = 0;
-      if (k < H.r) {
+      if (j < ML && k < H.r) {
         if (v < vp) {
           int s = 2 * v + half;
           if (s < H.S) val = (int)((H.u[k] >> (8 * s)) & 0xFF);
