@@ -230,7 +230,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   int* cexp = (int*)(col_out + NCOL);
   int* pexp = cexp + NCOL;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile addressing stays scalar
   int64_t g = 0, cstart;
   if (P.stage == 1) {
     cstart = tile * NCOL;
@@ -446,31 +447,31 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
         Fv[v] = (float)(f - d - e);      // I
       }
     }
-    // ---- residue-domain combines, canonical residues to the records ----
+    // ---- residue-domain combines, centred residues to the records ----
+    // (Alg. 1 combines; the Phase-A carrier takes them signed, |v| <= m/2 + 2.
+    // Rows past K hold zero products and are never stored.)
+    float rrv[4], riv[4];
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int row = 16 * mt + 4 * (lane >> 4) + v;
-      {
-        // centred residues of R and I (Alg. 1 combines); the Phase-A
-        // carrier takes them signed (|v| <= m/2 + 2).  Rows past K hold
-        // zero products and are never stored.
-        float rr, ri;
-        if (SUB != SUB_FP8) {
-          rr = reduce_f32(Dv[v], mf, imf);
-          ri = reduce_f32(Fv[v], mf, imf);
-        } else {
-          rr = reduce_f32(Dv[v] - Ev[v], mf, imf);
-          ri = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
-        }
-        rec[2 * v][i >> 1][i & 1] = (_Float16)rr;
-        rec[2 * v + 1][i >> 1][i & 1] = (_Float16)ri;
-        if (P.dbg_res && row < K) {
-          int64_t co = col_out[col];
-          if (co >= 0) {
-            int64_t el = co + (int64_t)row * P.s_out_t;
-            P.dbg_res[(el * 2) * R + i] = (uint16_t)(rr < 0.0f ? rr + mf : rr);
-            P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)(ri < 0.0f ? ri + mf : ri);
-          }
+      if (SUB != SUB_FP8) {
+        rrv[v] = reduce_f32(Dv[v], mf, imf);
+        riv[v] = reduce_f32(Fv[v], mf, imf);
+      } else {
+        rrv[v] = reduce_f32(Dv[v] - Ev[v], mf, imf);
+        riv[v] = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+      }
+      rec[2 * v][i >> 1][i & 1] = (_Float16)rrv[v];
+      rec[2 * v + 1][i >> 1][i & 1] = (_Float16)riv[v];
+    }
+    if (P.dbg_res) {  // canonical residue tap (tests only)
+      const int64_t co = col_out[col];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = 16 * mt + 4 * (lane >> 4) + v;
+        if (co >= 0 && row < K) {
+          int64_t el = co + (int64_t)row * P.s_out_t;
+          P.dbg_res[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
+          P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)(riv[v] < 0.0f ? riv[v] + mf : riv[v]);
         }
       }
     }
