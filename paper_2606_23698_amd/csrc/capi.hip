@@ -133,7 +133,6 @@ static obfft_status_t upload(obfft_plan_t plan, const void* host, size_t bytes, 
 static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) {
   plan->precision = opt->precision;
   int sub = opt->substrate;
-  if (sub == OBFFT_SUB_AUTO) sub = OBFFT_SUB_FP16;
   plan->substrate = sub;
   plan->kbits = plan->precision == OBFFT_PREC_FP32 ? 24 : 53;
   const int32_t* mods = plan->precision == OBFFT_PREC_FP32 ? kModFP32 : kModFP64;
@@ -145,6 +144,14 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   }
   std::string err;
   if (!build_modset(mods, r, plan->H, err)) return OBFFT_INVALID_VALUE;
+  // FP16 needs every modulus past the split to fit one slot per index; AUTO
+  // takes FP16 when the set allows it, else INT8
+  const int fp16_split = kFp16Split[plan->precision == OBFFT_PREC_FP32 ? 1 : 0];
+  bool fp16_ok = true;
+  for (int i = fp16_split; i < plan->H.r; i++) fp16_ok = fp16_ok && fp16_single_slot_ok(plan->H.m[i]);
+  if (sub == OBFFT_SUB_AUTO) sub = fp16_ok ? OBFFT_SUB_FP16 : OBFFT_SUB_INT8;
+  if (sub == OBFFT_SUB_FP16 && !fp16_ok) return OBFFT_UNSUPPORTED_SIZE;
+  plan->substrate = sub;
   int64_t kmax = 0;
   for (int a = 0; a < 3; a++) {
     int64_t N = plan->n[a];
@@ -181,7 +188,8 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
         }
         std::vector<uint8_t> bytes;
         OperandPlanes L;
-        build_operand_planes(plan->H, plan->roots[a], plan->n[a], plan->p[a], plan->q[a], st, d, sub, bytes, L);
+        build_operand_planes(plan->H, plan->roots[a], plan->n[a], plan->p[a], plan->q[a], st, d, sub, fp16_split,
+                             bytes, L);
         void* dptr = nullptr;
         obfft_status_t s = upload(plan, bytes.data(), bytes.size(), &dptr);
         if (s != OBFFT_SUCCESS) return s;

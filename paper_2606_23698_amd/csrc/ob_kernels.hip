@@ -165,6 +165,31 @@ __device__ __forceinline__ int f16_slot(int jc, int s) {
   return ((s >> 4) * NT + (jc >> 4)) * 1024 + ((jc & 15) + 16 * ((s & 15) >> 2)) * 16 + 4 * (s & 3);
 }
 
+// Byte offset of index s of column jc in one form's single-slot FP16 planes
+// (moduli past the split: slot s of chunk s / 32 sits in lane
+// (jc % 16) + 16 ((s % 32) / 8) at half s % 8).
+template <int NT>
+__device__ __forceinline__ int f16_slot1(int jc, int s) {
+  return ((s >> 5) * NT + (jc >> 4)) * 1024 + ((jc & 15) + 16 * ((s & 31) >> 3)) * 16 + 2 * (s & 7);
+}
+
+// Writes the residues r[0..KQ) of indices s0.. as single FP16 slots (KQ = 4
+// and 2 start on a multiple of KQ: one store inside one lane).
+template <int KQ, int NT>
+__device__ __forceinline__ void put_slots16(unsigned char* form_base, int jc, int s0, const float* r) {
+  if (KQ == 4) {
+    uint32_t w0 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r[0], r[1]));
+    uint32_t w1 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r[2], r[3]));
+    *(uint2*)(form_base + f16_slot1<NT>(jc, s0)) = make_uint2(w0, w1);
+  } else if (KQ == 2) {
+    *(uint32_t*)(form_base + f16_slot1<NT>(jc, s0)) =
+        __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r[0], r[1]));
+  } else {
+#pragma unroll
+    for (int u = 0; u < KQ; u++) *(_Float16*)(form_base + f16_slot1<NT>(jc, s0 + u)) = (_Float16)r[u];
+  }
+}
+
 // Writes the packed limb pairs of KQ consecutive indices s0.. (KQ = 4 starts
 // on a multiple of 4 and KQ = 2 on an even index: one store inside one lane).
 template <int KQ, int NT>
@@ -329,13 +354,16 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
                                                   P.amat_chmax * 1024 + lane * 16);
     }
     // FP16: planes of Re A, Im A and -Im A, CH16 chunks of 32 slots each
+    // (moduli past the split use chunk 0 only: one slot per index)
+    const bool split16 = i < kFp16Split[TGT];
+    const int nch = split16 ? nch16 : 1;
     v8h a16[3][CH16];
     if (SUB == SUB_FP16 && mt_active) {
 #pragma unroll
       for (int form = 0; form < 3; form++)
 #pragma unroll
         for (int ch = 0; ch < CH16; ch++)
-          if (ch < nch16)
+          if (ch < nch)
             a16[form][ch] = *(const v8h*)(amod + (((int64_t)form * P.amat_mt + mt) * P.amat_chmax + ch) * 1024 +
                                           lane * 16);
     }
@@ -343,13 +371,18 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
     // indices past K (when KQ does not divide K) store zero limbs: the FP16
     // planes must not see stray NaN patterns even against zero matrix slots
     uint32_t la[KQ] = {}, lb[KQ] = {}, ls[KQ] = {};
+    float ra16[KQ] = {}, rb16[KQ] = {};
 #pragma unroll
     for (int u = 0; u < KQ; u++) {
       int s = part * KQ + u;
       if (s < K) {
         if (SUB == SUB_FP16) {
-          la[u] = f16_limbs(residue_f64(ar[u], md, imd));
-          lb[u] = f16_limbs(residue_f64(br[u], md, imd));
+          ra16[u] = residue_f64(ar[u], md, imd);
+          rb16[u] = residue_f64(br[u], md, imd);
+          if (split16) {
+            la[u] = f16_limbs(ra16[u]);
+            lb[u] = f16_limbs(rb16[u]);
+          }
         } else if (SUB == SUB_INT8) {
           int ra = (int)__builtin_fma(-md, __builtin_rint(ar[u] * imd), ar[u]);
           int rb = (int)__builtin_fma(-md, __builtin_rint(br[u] * imd), br[u]);
@@ -372,8 +405,13 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
       put_limbs<KQ>(dig + 2 * kI8FormBytes, jc, s0, ls);
     }
     if (SUB == SUB_FP16 && s0 < K) {
-      put_limbs16<KQ, NT>(dig, jc, s0, la);
-      put_limbs16<KQ, NT>(dig + kF16FormBytes, jc, s0, lb);
+      if (split16) {
+        put_limbs16<KQ, NT>(dig, jc, s0, la);
+        put_limbs16<KQ, NT>(dig + kF16FormBytes, jc, s0, lb);
+      } else {
+        put_slots16<KQ, NT>(dig, jc, s0, ra16);
+        put_slots16<KQ, NT>(dig + kF16FormBytes, jc, s0, rb16);
+      }
     }
     __syncthreads();
     if (!mt_active) continue;
@@ -410,11 +448,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
       }
     } else if (SUB == SUB_FP16) {
       // four real products, accumulated exactly in FP32 (every partial sum
-      // is an integer below 2^23): R = Re A x~ - Im A y~, I = Im A x~ + Re A y~
+      // is an integer below 2^24): R = Re A x~ - Im A y~, I = Im A x~ + Re A y~
       v4f accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ch = 0; ch < CH16; ch++) {
-        if (ch < nch16) {
+        if (ch < nch) {
           v8h bx = *(const v8h*)(dig + ((ch * NT + nt) * 64 + lane) * 16);
           v8h by = *(const v8h*)(dig + kF16FormBytes + ((ch * NT + nt) * 64 + lane) * 16);
           accR = mfma_f16_16(a16[0][ch], bx, accR);

@@ -11,6 +11,14 @@ constexpr int kTapStride = 40;     // uint32 words per output in the CRT debug t
 
 enum Substrate { SUB_FP8 = 0, SUB_INT8 = 1, SUB_FP16 = 2, SUB_AUTO = 3 };
 
+// FP16 substrate: the first kFp16Split[precision] moduli of a set enter the
+// residue GEMM as two radix-128 limbs per index; every later modulus as one
+// FP16 slot per index, which needs 2 kMaxK floor(m/2) (floor(m/2) + 2) < 2^24
+// (the largest possible partial sum of a 32-term, two-product accumulation,
+// kept exact in FP32).  The default sets satisfy it from index 5 (r = 12:
+// 961, 841, ...) and 4 (r = 6: 961, 841).
+constexpr int kFp16Split[2] = {5, 4};
+
 // Everything the CRT epilogue needs: Sec. 4.2 (Phase A over canonical
 // residues, byte slices of u_k) and Sec. 5.1 (fractional lift, bias, M).
 struct CrtConsts {

@@ -298,9 +298,14 @@ static void matrix_entry(const std::vector<int64_t>& roots, int64_t N, int64_t p
   *sn = roots[2 * idx + 1] * (direction ? -1 : 1);
 }
 
+bool fp16_single_slot_ok(int m) {
+  int64_t h = m / 2;
+  return 2LL * kMaxK * h * (h + 2) < (1LL << 24);
+}
+
 void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
                           int64_t p, int64_t q, int stage, int direction, int substrate,
-                          std::vector<uint8_t>& bytes, OperandPlanes& L) {
+                          int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L) {
   int K = stage == 1 ? (int)q : (int)p;
   int G = stage == 1 ? 1 : (int)q;
   int MT = (K + 15) / 16;
@@ -329,7 +334,10 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
         }
       if (substrate == SUB_FP16) {
         // [form][M-tile][chunk][lane][8 halves]; slot 32 ch + 8 (lane / 16) + j
-        // holds limb weight 128^(slot % 2) of index slot / 2, folded mod m.
+        // holds limb weight 128^(slot % 2) of index slot / 2, folded mod m,
+        // for the first fp16_split moduli, and index `slot` itself (one FP16
+        // slot per index, chunk 0 only) for the others.
+        const bool split = i < fp16_split;
         int pw128 = 128 % m;
         for (int form = 0; form < 3; form++)
           for (int mt = 0; mt < MT; mt++)
@@ -338,7 +346,7 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
                 for (int j = 0; j < 8; j++) {
                   int t = 16 * mt + lane % 16;
                   int slot = 32 * ch + 8 * (lane / 16) + j;
-                  int s = slot / 2, e = slot % 2;
+                  int s = split ? slot / 2 : slot, e = split ? slot % 2 : 0;
                   int val = 0;
                   if (t < K && s < K) {
                     int a = cval[(form * K + t) * K + s];

@@ -98,6 +98,21 @@ def test_stage_residue_tap_matches_oracle_integers(gpu, substrate):
                 assert t2[line, slot, 1, k] == s2["im"][slot] % m
 
 
+@pytest.mark.parametrize("substrate", ["fp16", "int8", "fp8"])
+def test_permuted_modulus_set_gives_identical_bits(gpu, substrate):
+    """The reconstructed integers do not depend on the modulus order (any
+    admissible set has the capacity, Eq. capacity), so a permuted set must
+    reproduce the default plan's output bit for bit; for FP16 it moves
+    different moduli onto the limb-split and single-slot paths."""
+    api = _api()
+    shape = (8, 24, 32)
+    x = inputs.uniform(shape, 12)
+    mods = [2039, 2029, 2027, 1089, 1024, 487, 491, 511, 529, 625, 841, 961]
+    y0 = _run(api.Plan(shape), x, gpu)
+    y1 = _run(api.Plan(shape, substrate=substrate, moduli=mods), x, gpu)
+    assert np.array_equal(y0, y1)
+
+
 def test_inverse_and_adjoint(gpu):
     api = _api()
     shape = (16, 32, 8)

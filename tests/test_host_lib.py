@@ -74,6 +74,23 @@ def test_unsupported_and_invalid_sizes():
     assert e.value.status == 1
 
 
+def test_fp16_substrate_rejects_a_large_modulus_past_the_split():
+    """FP16 takes one slot per index for moduli 5.. of an FP64 set, which is
+    exact only when 64 floor(m/2) (floor(m/2) + 2) < 2^24 (m <= 961 of the
+    default set); 1089 at index 5 violates it."""
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import ObfftError
+    h = 1089 // 2
+    assert 64 * h * (h + 2) >= 2 ** 24
+    h = 961 // 2
+    assert 64 * h * (h + 2) < 2 ** 24
+    mods = [2039, 2029, 2027, 961, 1024, 1089, 841, 625, 529, 511, 491, 487]
+    assert sorted(mods) == sorted(K.MODULI_FP64)
+    with pytest.raises(ObfftError) as e:
+        api.Plan((32, 32, 32), substrate="fp16", moduli=mods)
+    assert e.value.status == 2   # OBFFT_UNSUPPORTED_SIZE
+
+
 def test_status_strings_and_taps_layout():
     from paper_2606_23698_amd import api
     from paper_2606_23698_amd._lib import status_string
