@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -65,6 +67,57 @@ def stage_durations(plan, x, y, ws_a, reps):
     return sum(durs) / len(durs), durs
 
 
+def precision_sweep(api, x, y_ref, steps):
+    """The other substrates (bit-identical outputs) and the FP32 target at the same size."""
+    import torch
+    out = {}
+    for sub in ("fp8", "int8"):
+        plan = api.Plan(tuple(x.shape), substrate=sub)
+        y = torch.empty_like(x)
+        ms, _ = time_steps(lambda: plan.forward(x, y), steps, 1)
+        same = bool(torch.equal(torch.view_as_real(y), torch.view_as_real(y_ref)))
+        out[sub] = {"ms": round(ms, 3), "bit_identical_to_default": same}
+        print(f"[bench] {sub}: {ms:.2f} ms, identical={same}", file=sys.stderr, flush=True)
+        del y, plan
+        torch.cuda.empty_cache()
+    x32 = x.to(torch.complex64)
+    plan = api.Plan(tuple(x.shape), precision="fp32")
+    y32 = torch.empty_like(x32)
+    ms, _ = time_steps(lambda: plan.forward(x32, y32), steps, 1)
+    err = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y_ref) / torch.linalg.vector_norm(y_ref))
+    out["fp32_target"] = {"ms": round(ms, 3), "rel_l2_vs_fp64": err,
+                          "hbm_roof_ms": round(48.0 * x.numel() / (HBM_PEAK_GBS * 1e9) * 1e3, 3)}
+    print(f"[bench] fp32 target: {ms:.2f} ms, rel err vs FP64 {err:.2e}", file=sys.stderr, flush=True)
+    del x32, y32, plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_throughput(api, inputs, steps):
+    """64 uneven transforms: one persistent launch per Bailey pass under a
+    hipGraph, against a loop of single-transform plans."""
+    import torch
+    shapes, _ = inputs.batch_shapes(3, 64)
+    xs = [inputs.device_uniform(s, 3 + i) for i, s in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    bp = api.BatchPlan(shapes)
+    ms_b, _ = time_steps(lambda: bp.forward(xs, ys), steps, 1)
+    plans = [api.get_plan(s) for s in shapes]
+    ys2 = [torch.empty_like(x) for x in xs]
+
+    def loop():
+        for pl, x, o in zip(plans, xs, ys2):
+            pl.forward(x, o)
+    ms_l, _ = time_steps(loop, steps, 1)
+    same = all(torch.equal(torch.view_as_real(a), torch.view_as_real(b)) for a, b in zip(ys, ys2))
+    elems = sum(int(np.prod(s)) for s in shapes)
+    print(f"[bench] batch64: {ms_b:.2f} ms graph vs {ms_l:.2f} ms loop", file=sys.stderr, flush=True)
+    return {"transforms": len(shapes), "elements": elems, "ms": round(ms_b, 3), "loop_ms": round(ms_l, 3),
+            "speedup_vs_loop": round(ms_l / ms_b, 3), "bit_identical_to_loop": same,
+            "workload": "64 complex FP64 3-D FFTs, extents from {64,96,128,192,256} per axis (seed 3), "
+                        "uniform[-1,1)"}
+
+
 def cpu_baseline(N, pq, target_s=12.0):
     """The exact-pipeline oracle on a bounded sample of axis passes, scaled to one transform.
 
@@ -104,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=2)
     ap.add_argument("--no-native", action="store_true", help="skip the native FP64 comparator")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the FP8 / INT8 / FP32-target sweep")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-transform batched measurement")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the input (a known-size reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -179,6 +234,12 @@ def main():
                      "kernel": "ob_stage_kernel", "avg_launch_ms": round(stage_ms, 3),
                      "algorithmic_per_launch": f"{C_EPI_MIN} integer ops x {n_out_launch} outputs"},
     }
+    if not args.no_sweep:
+        line["precision_sweep"] = precision_sweep(api, x, y, max(2, min(args.steps, 3)))
+    if not args.no_batch:
+        del x, y
+        torch.cuda.empty_cache()
+        line["batch64"] = batch_throughput(api, inputs, max(2, min(args.steps, 5)))
     if not args.no_cpu:
         try:
             line["cpu_baseline"] = cpu_baseline(N, (info["p"][2], info["q"][2]))

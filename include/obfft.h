@@ -200,8 +200,9 @@ obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
 
 /* Batched transforms: `count` independent FP64 forward transforms of possibly
  * different shapes (host int64 [count][3]).  Each of the six Bailey passes
- * (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs as ONE persistent
- * launch over the tiles of every member; the six launches are captured once
+ * (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs as ONE launch over
+ * the tiles of every member (one workgroup per tile, each finding its member
+ * in a device descriptor table); the six launches are captured once
  * in a hipGraph and replayed.  Members with equal shapes share one plan.
  * Outputs are bit-identical to fft3d_z2z_forward on each member.  The batch
  * owns a workspace of the summed member sizes, allocated on first use.

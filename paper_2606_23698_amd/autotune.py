@@ -3,7 +3,8 @@
 Candidates per axis are the admissible splits N = p q (both even, both <= 32;
 p <= q and p > q are different plans with different output bits, as the
 factorisation fixes which roundings happen where); candidates for the
-substrate are FP8 and INT8 (bit-identical outputs).  Every candidate plan is
+substrate are FP16, INT8 and FP8 (bit-identical outputs for one
+factorisation).  Every candidate plan is
 timed on the device with HIP events (median of `reps` forward transforms on
 a seeded input) and the fastest is cached in a JSON file keyed by shape,
 precision and device name ($OBFFT_AUTOTUNE_CACHE, default
@@ -69,9 +70,26 @@ def _time_plan(plan, x, reps):
     return ts[len(ts) // 2]
 
 
-def tune(shape, precision="fp64", substrates=("int8", "fp8"), reps=3, max_candidates=16,
+def _try_time(shape, precision, sub, pq, x, reps):
+    from ._lib import ObfftError
+    try:
+        plan = api.Plan(shape, precision=precision, substrate=sub, pq=pq)
+    except ObfftError:
+        return None  # e.g. FP16 with a modulus set it cannot host
+    try:
+        return _time_plan(plan, x, reps)
+    finally:
+        plan.close()
+
+
+def tune(shape, precision="fp64", substrates=("fp16", "int8", "fp8"), reps=3, max_splits=2,
          use_cache=True):
-    """Returns {"substrate", "pq", "ms"} for the fastest candidate plan of `shape`."""
+    """Returns {"substrate", "pq", "ms"} for the fastest candidate plan of `shape`.
+
+    Phase 1 times every combination of the `max_splits` most balanced splits
+    per axis on the first substrate; phase 2 times the other substrates on the
+    winning factorisation.
+    """
     shape = tuple(int(n) for n in shape)
     dev = torch.cuda.get_device_name(0)
     key = f"{shape[0]}x{shape[1]}x{shape[2]}/{precision}/{dev}"
@@ -81,17 +99,25 @@ def tune(shape, precision="fp64", substrates=("int8", "fp8"), reps=3, max_candid
     per_axis = [splits(n) for n in shape]
     if any(not s for s in per_axis):
         raise ValueError(f"no admissible factorisation for {shape}")
-    # keep the candidate count bounded: the splits nearest sqrt(N) first
-    per_axis = [sorted(s, key=lambda pq: abs(pq[0] - pq[1]))[:2] for s in per_axis]
-    cands = list(itertools.product(substrates, itertools.product(*per_axis)))[:max_candidates]
+    per_axis = [sorted(s, key=lambda pq: (abs(pq[0] - pq[1]), pq[0]))[:max_splits] for s in per_axis]
     dtype = torch.complex128 if precision == "fp64" else torch.complex64
     x = inputs.device_uniform(shape, 0, dtype=dtype)
     best = None
-    for sub, pq in cands:
-        plan = api.Plan(shape, precision=precision, substrate=sub, pq=pq)
-        ms = _time_plan(plan, x, reps)
-        plan.close()
-        if best is None or ms < best["ms"]:
+    for pq in itertools.product(*per_axis):
+        for sub in substrates:
+            ms = _try_time(shape, precision, sub, pq, x, reps)
+            if ms is not None:
+                break
+        if ms is not None and (best is None or ms < best["ms"]):
+            best = {"substrate": sub, "pq": [list(v) for v in pq], "ms": ms}
+    if best is None:
+        raise ValueError(f"no plan could be built for {shape}")
+    pq = tuple(tuple(v) for v in best["pq"])
+    for sub in substrates:
+        if sub == best["substrate"]:
+            continue
+        ms = _try_time(shape, precision, sub, pq, x, reps)
+        if ms is not None and ms < best["ms"]:
             best = {"substrate": sub, "pq": [list(v) for v in pq], "ms": ms}
     if use_cache:
         cache = _load()

@@ -537,8 +537,9 @@ extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* 
 // ---- batched transforms ----
 //
 // All member transforms of a batch run pass by pass (axis n3 stage 1, n3
-// stage 2, n2 ..., n1 stage 2): each pass is ONE persistent launch over the
-// tiles of every member, driven by a device table of stage descriptors.  The
+// stage 2, n2 ..., n1 stage 2): each pass is ONE launch over the tiles of
+// every member (a workgroup per tile), driven by a device table of stage
+// descriptors.  The
 // six launches are captured once in a hipGraph and replayed; only the table
 // (with the callers' pointers) is re-uploaded per call.
 static const int kPassAxis[6] = {2, 2, 1, 1, 0, 0};
@@ -623,11 +624,9 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     obfft_plan_destroy(bp);
     return OBFFT_HIP_ERROR;
   }
-  int dev = 0, ncu = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    ncu = prop.multiProcessorCount;
-  for (int pass = 0; pass < 6; pass++) bp->batch_grid[pass] = std::min<int64_t>(bp->batch_total[pass], (int64_t)ncu * 8);
+  // one workgroup per tile: the hardware dispatcher balances the uneven
+  // members, and no loop state stays live across tiles
+  for (int pass = 0; pass < 6; pass++) bp->batch_grid[pass] = bp->batch_total[pass];
   bp->members_of_batch = per;
   *out = bp;
   return OBFFT_SUCCESS;

@@ -195,61 +195,60 @@ __global__ __launch_bounds__(kNatThreads) void native_axis_kernel(const double2*
 // lanes along a line, true puts them on neighbouring lines, so that global
 // loads and stores are coalesced in both cases.
 
-// Length-R DFT in registers, decimation in time with radix 2 or 3 steps;
-// twiddles w_R^t are read from `tw` (the axis table w_N^t) at stride N/R.
+// Length-R DFT in registers, in place, decimation in frequency: one radix-r
+// step (r = 4, 2 or 3) turns v[j + m a] (m = R / r) into the r blocks
+// y_b[j] = w_R^{j b} sum_a v[j + m a] w_r^{a b} stored at v[m b + j], and
+// block b then holds, after its own length-m transform, X[b + r k'].  No
+// copies: the output X[k] is left at position pos(k), a digit reversal known
+// at compile time.  Twiddles w_R^t come from the axis table at stride N / R.
 template <int R, int DIR>
 struct RegDft {
-  __device__ __forceinline__ static void run(double2* v, const double2* tw, int tstride) {
+  static constexpr int r = (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : 3;
+  static constexpr int m = R / r;
+
+  __host__ __device__ static constexpr int pos(int k) {
     if constexpr (R == 1) {
-      return;
+      return 0;
     } else {
-      constexpr int r = (R % 2 == 0) ? 2 : 3;
-      constexpr int m = R / r;
-      double2 sub[r][m];
+      return m * (k % r) + RegDft<m, DIR>::pos(k / r);
+    }
+  }
+
+  __device__ __forceinline__ static void run(double2* v, const double2* tw, int tstride) {
+    if constexpr (R > 1) {
 #pragma unroll
-      for (int a = 0; a < r; a++)
+      for (int j = 0; j < m; j++) {
+        double2 t[r];
 #pragma unroll
-        for (int j = 0; j < m; j++) sub[a][j] = v[a + r * j];
-#pragma unroll
-      for (int a = 0; a < r; a++) RegDft<m, DIR>::run(sub[a], tw, tstride * r);
-#pragma unroll
-      for (int k = 0; k < m; k++) {
+        for (int a = 0; a < r; a++) t[a] = v[j + m * a];
+        dft_r<r, DIR>(t);
 #pragma unroll
         for (int b = 0; b < r; b++) {
-          double2 acc = sub[0][k];
-#pragma unroll
-          for (int a = 1; a < r; a++) {
-            const int t = (a * (k + m * b)) % R;
-            double2 x = sub[a][k];
-            if (t == 0) {
-              acc.x += x.x;
-              acc.y += x.y;
-            } else if (2 * t == R) {
-              acc.x -= x.x;
-              acc.y -= x.y;
-            } else if (4 * t == R) {
-              // w = -i DIR
-              acc.x += DIR * x.y;
-              acc.y -= DIR * x.x;
-            } else if (4 * t == 3 * R) {
-              acc.x -= DIR * x.y;
-              acc.y += DIR * x.x;
-            } else {
-              double2 w = tw[t * tstride];
-              double wy = DIR * w.y;
-              acc.x = __builtin_fma(x.x, w.x, __builtin_fma(-x.y, wy, acc.x));
-              acc.y = __builtin_fma(x.x, wy, __builtin_fma(x.y, w.x, acc.y));
-            }
+          const int e = j * b;  // twiddle w_R^e, e < R
+          double2 x = t[b];
+          if (e == 0) {
+          } else if (2 * e == R) {
+            x = make_double2(-x.x, -x.y);
+          } else if (4 * e == R) {
+            x = make_double2(DIR * x.y, -DIR * x.x);
+          } else if (4 * e == 3 * R) {
+            x = make_double2(-DIR * x.y, DIR * x.x);
+          } else {
+            const double2 w = tw[e * tstride];
+            const double wy = DIR * w.y;
+            x = make_double2(__builtin_fma(x.x, w.x, -x.y * wy), __builtin_fma(x.x, wy, x.y * w.x));
           }
-          v[k + m * b] = acc;
+          v[j + m * b] = x;
         }
       }
+#pragma unroll
+      for (int b = 0; b < r; b++) RegDft<m, DIR>::run(v + m * b, tw, tstride * r);
     }
   }
 };
 
 template <int R1, int R2, bool STRIDED, int DIR>
-__global__ __launch_bounds__(kNatThreads) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
+__global__ __launch_bounds__(kNatThreads) __attribute__((amdgpu_waves_per_eu(2))) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
                                                                    int64_t nlines, const double2* tw,
                                                                    double post_scale) {
   constexpr int N = R1 * R2;
@@ -276,12 +275,14 @@ __global__ __launch_bounds__(kNatThreads) void native_4step_kernel(const double2
   for (int n1 = 0; n1 < R1; n1++)
     v[n1] = valid1 ? src[(int64_t)(n1 * R2 + n2) * inner] : make_double2(0.0, 0.0);
   RegDft<R1, DIR>::run(v, tw, N / R1);
+  // X1[k1] sits at v[pos(k1)]; twiddle w_N^{n2 k1}
 #pragma unroll
   for (int k1 = 1; k1 < R1; k1++) {
+    const int pk = RegDft<R1, DIR>::pos(k1);
     double2 w = tw[(n2 * k1) % N];
     double wy = DIR * w.y;
-    double2 a = v[k1];
-    v[k1] = make_double2(__builtin_fma(a.x, w.x, -a.y * wy), __builtin_fma(a.x, wy, a.y * w.x));
+    double2 a = v[pk];
+    v[pk] = make_double2(__builtin_fma(a.x, w.x, -a.y * wy), __builtin_fma(a.x, wy, a.y * w.x));
   }
   // step 2 mapping: task (line, k1); R1 <= R2 so LPW * R1 <= threads
   int l2, k1t;
@@ -298,7 +299,10 @@ __global__ __launch_bounds__(kNatThreads) void native_4step_kernel(const double2
 #pragma unroll
   for (int c = 0; c < 2; c++) {
 #pragma unroll
-    for (int k1 = 0; k1 < R1; k1++) plane[l1 * LS + k1 * (R2 + 1) + n2] = c ? v[k1].y : v[k1].x;
+    for (int k1 = 0; k1 < R1; k1++) {
+      const int pk = RegDft<R1, DIR>::pos(k1);
+      plane[l1 * LS + k1 * (R2 + 1) + n2] = c ? v[pk].y : v[pk].x;
+    }
     __syncthreads();
     if (active2) {
 #pragma unroll
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kNatThreads) void native_4step_kernel(const double2
   double2* dst = out + o2 * N * inner + i2;
 #pragma unroll
   for (int k2 = 0; k2 < R2; k2++) {
-    double2 x = u[k2];
+    double2 x = u[RegDft<R2, DIR>::pos(k2)];
     if (post_scale != 1.0) x = make_double2(x.x * post_scale, x.y * post_scale);
     dst[(int64_t)(k1t + R1 * k2) * inner] = x;
   }

@@ -68,14 +68,16 @@ __device__ __forceinline__ uint32_t subc(uint32_t a, uint32_t b, uint32_t bin, u
 //
 // Inputs are the Phase-A partials after the lane-half swap: register pair v
 // holds (xv[v], yv[v]) = (partial 2v, partial 2v+1) of P for v < VP and of Z
-// for VP <= v < VP + VZ.  Every partial is an FP32 value 2^23 + P exactly,
-// i.e. its bit pattern is 0x4B000000 + P (the biased deposit of Alg. 2; the
-// implicit bias is removed through the constant K0 / Czh).
+// for VP <= v < VP + VZ.  Every partial is the FP32 value seed_j + P_j in the
+// binade [2^23, 2^24), so its bit pattern is bits(seed_j) + P_j: the biased
+// deposit of Alg. 2, whose bias (with every other additive constant of the
+// lift) the host folds into the seeds.
 template <int S, int TZ, int NW>
 struct Epilogue {
   static constexpr int VP = (S + 1) / 2;
   static constexpr int VZ = (TZ + 1) / 2;
   static constexpr int NV = VP + VZ;
+  static_assert(TZ == 6, "the lift sum reads six slices");
 
   __device__ __forceinline__ static uint32_t pbits(const float* xv, const float* yv, int s) {
     return __float_as_uint((s & 1) ? yv[s >> 1] : xv[s >> 1]);
@@ -84,57 +86,103 @@ struct Epilogue {
     return __float_as_uint((t & 1) ? yv[VP + (t >> 1)] : xv[VP + (t >> 1)]);
   }
 
-  // Biased deposits: E_b = sum_s bits(P_s) 2^{8s}, as 32-bit words (carry
-  // sweep folded into 64-bit column sums of four slices each).
-  __device__ __forceinline__ static void deposits(const float* xv, const float* yv, uint32_t* w,
-                                                  uint32_t* w_top) {
+  // Column of the four patterns b0..b3 at bits 32c, 32c+8, 32c+16, 32c+24:
+  // the low word L (mod 2^32) and the spill H into word c+1.  b1 << 8 fits
+  // beside b0 (b0 < 2^31, (b1 << 8) mod 2^32 < 2^31) and drops b1's top byte,
+  // which is the constant 0x4B of every pattern (put back by the seeds); the
+  // spills of b2 and b3 are kept, with the two carries of L.
+  template <int NB>
+  __device__ __forceinline__ static void column(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t& L,
+                                                uint32_t& H) {
+    uint32_t l = b0, h = 0, cy;
+    if (NB > 1) l += b1 << 8;
+    if (NB > 2) {
+      l = addc(l, b2 << 16, 0u, &cy);
+      h = (b2 >> 16) + cy;
+    }
+    if (NB > 3) {
+      l = addc(l, b3 << 24, 0u, &cy);
+      h = h + (b3 >> 8) + cy;
+    }
+    L = l;
+    H = h;
+  }
+
+  // W = sum_s bits_s 256^s - dropped + khi 2^(32(NW-1))  (mod 2^(32 NW)).
+  __device__ __forceinline__ static void deposits(const float* xv, const float* yv, uint32_t khi, uint32_t* w) {
     constexpr int NC = (S + 3) / 4;
-    uint64_t col[NC];
+    uint32_t L[NC], H[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-      uint64_t x = pbits(xv, yv, 4 * c);
-#pragma unroll
-      for (int j = 1; j < 4; j++)
-        if (4 * c + j < S) x += (uint64_t)pbits(xv, yv, 4 * c + j) << (8 * j);
-      col[c] = x;
+      const int nb = S - 4 * c < 4 ? S - 4 * c : 4;
+      uint32_t b0 = pbits(xv, yv, 4 * c);
+      uint32_t b1 = nb > 1 ? pbits(xv, yv, 4 * c + 1) : 0u;
+      uint32_t b2 = nb > 2 ? pbits(xv, yv, 4 * c + 2) : 0u;
+      uint32_t b3 = nb > 3 ? pbits(xv, yv, 4 * c + 3) : 0u;
+      if (nb == 4) column<4>(b0, b1, b2, b3, L[c], H[c]);
+      else if (nb == 3) column<3>(b0, b1, b2, b3, L[c], H[c]);
+      else if (nb == 2) column<2>(b0, b1, b2, b3, L[c], H[c]);
+      else column<1>(b0, b1, b2, b3, L[c], H[c]);
     }
-    uint64_t acc = col[0];
-    w[0] = (uint32_t)acc;
+    w[0] = L[0];
+    uint32_t cy = 0;
 #pragma unroll
-    for (int c = 1; c < NC; c++) {
-      acc = (acc >> 32) + col[c];
-      w[c] = (uint32_t)acc;
+    for (int i = 1; i < NW; i++) {
+      uint32_t a = i < NC ? L[i] : 0u;
+      uint32_t b = i - 1 < NC ? H[i - 1] : 0u;
+      w[i] = addc(a, b, cy, &cy);
     }
-    *w_top = (uint32_t)(acc >> 32);
+    w[NW - 1] += khi;
   }
 
-  // zhat = round-half-up(2^-48 sum_t Z_t 256^t) (Sec. 5.1).
-  __device__ __forceinline__ static uint32_t zhat(const float* xv, const float* yv, uint64_t czh) {
-    uint64_t z = 0;
-#pragma unroll
-    for (int t = 0; t < TZ; t++) z += (uint64_t)zbits(xv, yv, t) << (8 * t);
-    return (uint32_t)((z + czh) >> 48);
+  // zhat + zoff = round-half-up(2^-48 sum_t Z_t 256^t) + zoff (Sec. 5.1): word
+  // 1 of the seeded sum (the seeds carry 2^47 and zoff 2^48), bits 16..31.
+  __device__ __forceinline__ static uint32_t zhat(const float* xv, const float* yv, uint32_t zhi) {
+    uint32_t L0, H0;
+    column<4>(zbits(xv, yv, 0), zbits(xv, yv, 1), zbits(xv, yv, 2), zbits(xv, yv, 3), L0, H0);
+    (void)L0;
+    uint32_t w1 = H0 + zbits(xv, yv, 4) + (zbits(xv, yv, 5) << 8) + zhi;
+    return w1 >> 16;
   }
 
-  // X = E + M/2 - zhat M (mod 2^(32 NW)), then the two-sided correction into
-  // [0, M) and R = X - M/2 in [-M/2, M/2) (Sec. 5.1, Alg. 2).
-  __device__ __forceinline__ static void lift(const uint32_t* w, uint32_t zh, const CrtConsts& C,
-                                              uint32_t* R) {
-    uint32_t zm[NW];
+  // Full pattern sum sum_s bits_s 256^s mod 2^160 (debug taps only).
+  __device__ __forceinline__ static void deposits_full(const float* xv, const float* yv, uint32_t* w5) {
+    uint64_t acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      int pos = 8 * s, wi = pos >> 5, sh = pos & 31;
+      uint64_t v = (uint64_t)pbits(xv, yv, s) << sh;
+      acc[wi] += (uint32_t)v;
+      if (wi + 1 < 5) acc[wi + 1] += v >> 32;
+    }
+    uint64_t cy = 0;
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+      uint64_t t = acc[i] + cy;
+      w5[i] = (uint32_t)t;
+      cy = t >> 32;
+    }
+  }
+
+  __device__ __forceinline__ static void times_m(uint32_t zh, const CrtConsts& C, uint32_t* zm) {
     uint64_t p = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
       p = (uint64_t)zh * C.M[i] + (p >> 32);
       zm[i] = (uint32_t)p;
     }
-    uint32_t X[NW], cy = 0, bw = 0;
+  }
+
+  // Exact two-sided lift (Sec. 5.1, Alg. 2): with W = E + M/2 + zoff M,
+  // X = W - (zhat + zoff) M = E - zhat M + M/2, corrected into [0, M) from
+  // either side, and R = X - M/2 in [-M/2, M/2).
+  __device__ __forceinline__ static void lift_exact(const uint32_t* w, uint32_t zh, const CrtConsts& C,
+                                                    uint32_t* R) {
+    uint32_t zm[NW], X[NW], Y[NW], Z[NW], bw = 0, cy = 0;
+    times_m(zh, C, zm);
 #pragma unroll
-    for (int i = 0; i < NW; i++) X[i] = addc(w[i], C.K0[i], cy, &cy);
-#pragma unroll
-    for (int i = 0; i < NW; i++) X[i] = subc(X[i], zm[i], bw, &bw);
-    uint32_t Y[NW], Z[NW];
+    for (int i = 0; i < NW; i++) X[i] = subc(w[i], zm[i], bw, &bw);
     bw = 0;
-    cy = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) Y[i] = subc(X[i], C.M[i], bw, &bw);
 #pragma unroll
@@ -146,6 +194,26 @@ struct Epilogue {
     for (int i = 0; i < NW; i++) {
       uint32_t s = xneg ? Z[i] : (ypos ? Y[i] : X[i]);
       R[i] = subc(s, C.Mhalf[i], bw, &bw);
+    }
+  }
+
+  // Two-sided lift under the capacity bound (Eq. capacity): with W = E +
+  // zoff M, X = E - zhat M is the output C itself or C -/+ M.  |C| is below
+  // 2^(cap - 1), far under M/4, so the top 64 bits of X decide the side:
+  // above thr subtract M, below -thr add M.  Equals the exact lift for every
+  // value the stage kernels produce.
+  __device__ __forceinline__ static void lift_capacity(const uint32_t* w, uint32_t zh, const CrtConsts& C,
+                                                       uint32_t* R) {
+    uint32_t zm[NW], X[NW], bw = 0, cy = 0;
+    times_m(zh, C, zm);
+#pragma unroll
+    for (int i = 0; i < NW; i++) X[i] = subc(w[i], zm[i], bw, &bw);
+    const int64_t top = (int64_t)(((uint64_t)X[NW - 1] << 32) | X[NW - 2]);
+    const bool hi = top > C.thr, lo = top < -C.thr;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      uint32_t d = hi ? C.negM[i] : (lo ? C.M[i] : 0u);
+      R[i] = addc(X[i], d, cy, &cy);
     }
   }
 };

@@ -221,10 +221,13 @@ __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, const v16f& see
   }
 }
 
-__device__ __forceinline__ v16f phase_a_seed() {
+// Accumulator seeds of the Phase-A MFMA: register v of lane half h holds
+// partial 2v + h, seeded with tbl[2v + h] (1.5 * 2^23 plus the folded lift
+// constants of that slice).
+__device__ __forceinline__ v16f phase_a_seed(const float* tbl, int h) {
   v16f c;
 #pragma unroll
-  for (int v = 0; v < 16; v++) c[v] = 12582912.0f;  // 1.5 * 2^23
+  for (int v = 0; v < 16; v++) c[v] = h ? tbl[2 * v + 1] : tbl[2 * v];
   // opaque to the optimiser: the seed stays resident in 16 VGPRs instead of
   // being rematerialised before every MFMA
   asm volatile("" : "+v"(c));
@@ -522,7 +525,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   // high half moduli ML .. r-1; one swap per packed pair hands each half the
   // other half's share (b1: the low lanes' outputs, b2: the high lanes').
   const v8h aop = *(const v8h*)(P.phaseA + lane * 8);
-  const v16f seed = phase_a_seed();
+  const v16f seed = phase_a_seed(C.seed_c, lane >> 5);
   const int64_t co = col_out[col];
   const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
   typename TT::T re_part = 0;
@@ -543,11 +546,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
     v8h b2 = __builtin_bit_cast(v8h, make_uint4(b2w[0], b2w[1], b2w[2], b2w[3]));
     float xv[EP::NV], yv[EP::NV];
     phase_a<EP::NV>(aop, b1, b2, seed, xv, yv);
-    uint32_t wv[(TT::S + 3) / 4 + 1];
-    EP::deposits(xv, yv, wv, &wv[(TT::S + 3) / 4]);
-    uint32_t zh = EP::zhat(xv, yv, C.Czh);
+    uint32_t wv[TT::NW];
+    EP::deposits(xv, yv, C.khi_c, wv);
+    const uint32_t zh = EP::zhat(xv, yv, C.zhi);
     uint32_t Rw[TT::NW];
-    EP::lift(wv, zh, C, Rw);
+    EP::lift_capacity(wv, zh, C, Rw);
     typename TT::T y;
     if (TGT == 0)
       y = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
@@ -573,26 +576,24 @@ __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P,
   stage_tile<SUB, TGT, KMAX>(P, MC, C, (int64_t)blockIdx.x);
 }
 
-// Persistent batched stage: every workgroup walks the tiles of all
-// transforms of one Bailey pass.  descs[d] describes transform d's stage and
-// prefix[d] is the index of its first tile (prefix[ndesc] = total tiles).
+// Batched stage: one workgroup per tile of all transforms of one Bailey
+// pass.  descs[d] describes transform d's stage and prefix[d] is the index
+// of its first tile (prefix[ndesc] = total tiles = the grid).
 template <int SUB, int TGT, int KMAX>
 __global__ __launch_bounds__(kThreads) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ prefix, int ndesc,
                                                             const ModConsts MC, const CrtConsts C) {
-  const int64_t total = prefix[ndesc];
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = ndesc - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (prefix[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads become scalar
-    const StageParams P = descs[lo];
-    stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo]);
-    __syncthreads();
+  const int64_t t = blockIdx.x;
+  if (t >= prefix[ndesc]) return;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid;
+    else hi = mid - 1;
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads become scalar
+  const StageParams P = descs[lo];
+  stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo]);
 }
 
 // ---- standalone CRT reconstruction (unit-level access to Phase A / B) ----
@@ -619,13 +620,12 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
     b2[j] = (use && o2 < n) ? (_Float16)(float)residues[o2 * R + k] : (_Float16)0.0f;
   }
   float xv[EP::NV], yv[EP::NV];
-  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(), xv, yv);
-  constexpr int NC = (TT::S + 3) / 4;
-  uint32_t wv[NC + 1];
-  EP::deposits(xv, yv, wv, &wv[NC]);
-  uint32_t zh = EP::zhat(xv, yv, C.Czh);
+  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(C.seed_x, h), xv, yv);
+  uint32_t wv[TT::NW];
+  EP::deposits(xv, yv, C.khi_x, wv);
+  const uint32_t zh = EP::zhat(xv, yv, C.zhi);
   uint32_t Rw[TT::NW];
-  EP::lift(wv, zh, C, Rw);
+  EP::lift_exact(wv, zh, C, Rw);
   const int64_t o = base + lane;
   if (o < n) {
     const int ex = exps[o];
@@ -635,14 +635,13 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
       ((float*)out)[o] = pack_f32<TT::NW>(Rw, ex);
     if (taps) {
       uint32_t* tp = taps + o * kTapStride;
-      for (int s = 0; s < TT::S; s++) tp[s] = EP::pbits(xv, yv, s) - 0x4B400000u;
-      for (int t = 0; t < TT::TZ; t++) tp[16 + t] = EP::zbits(xv, yv, t) - 0x4B400000u;
-      // E = E_b - Bp (mod 2^160)
-      uint32_t E[5], bw = 0;
-      for (int i = 0; i < 5; i++) {
-        uint32_t wi = i <= NC ? wv[i] : 0u;
-        E[i] = subc(wi, C.Bp5[i], bw, &bw);
-      }
+      constexpr int VP = EP::VP;
+      for (int s2 = 0; s2 < TT::S; s2++) tp[s2] = EP::pbits(xv, yv, s2) - __float_as_uint(C.seed_x[s2]);
+      for (int t = 0; t < TT::TZ; t++) tp[16 + t] = EP::zbits(xv, yv, t) - __float_as_uint(C.seed_x[2 * VP + t]);
+      // E = sum_s bits_s 256^s - sum_s bits(seed_s) 256^s  (mod 2^160)
+      uint32_t Ef[5], E[5], bw = 0;
+      EP::deposits_full(xv, yv, Ef);
+      for (int i = 0; i < 5; i++) E[i] = subc(Ef[i], C.Bp5[i], bw, &bw);
       for (int i = 0; i < 5; i++) tp[24 + i] = E[i];
       tp[29] = zh - C.zoff;
       for (int i = 0; i < 4; i++) tp[30 + i] = i < TT::NW ? Rw[i] : (uint32_t)((int32_t)Rw[TT::NW - 1] >> 31);

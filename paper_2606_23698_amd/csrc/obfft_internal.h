@@ -19,8 +19,19 @@ enum Substrate { SUB_FP8 = 0, SUB_INT8 = 1, SUB_FP16 = 2, SUB_AUTO = 3 };
 // 961, 841, ...) and 4 (r = 6: 961, 841).
 constexpr int kFp16Split[2] = {5, 4};
 
-// Everything the CRT epilogue needs: Sec. 4.2 (Phase A over canonical
-// residues, byte slices of u_k) and Sec. 5.1 (fractional lift, bias, M).
+// Everything the CRT epilogue needs: Sec. 4.2 (Phase A, byte slices of
+// u_k) and Sec. 5.1 (fractional lift, bias, M).
+//
+// Phase A leaves partial j of an output in accumulator register j / 2 of
+// lane half j % 2, as the FP32 value seed[j] + P_j with seed[j] =
+// 1.5 * 2^23 + delta_j (delta_j < 2^16, |P_j| < 2^22: one binade), so its bit
+// pattern is bits(seed[j]) + P_j.  The deltas fold every additive constant
+// of the lift into the MFMA: the implicit bias of the bit patterns, the top
+// byte that the fast deposit drops (see Epilogue), the offset zoff M that
+// keeps zhat unsigned for centred residues, and M / 2 for the exact lift.
+// Whatever does not fit in the last slice's 16 bits is added to the top word
+// (khi, zhi).  Two seed sets: `x` for the exact two-sided lift, `c` for the
+// capacity lift of the stage kernels (no M / 2).
 struct CrtConsts {
   int r;                 // number of moduli
   int S;                 // byte slices of u_k
@@ -28,10 +39,14 @@ struct CrtConsts {
   int nwords;            // 32-bit words of the lift arithmetic (4: FP64 set, 3: FP32 set)
   uint32_t M[4];         // M, little-endian words
   uint32_t Mhalf[4];     // M / 2
-  uint32_t K0[4];        // (M/2 - Bp + zoff M) mod 2^128; Bp = implicit bias of the deposits
-  uint64_t Czh;          // (2^47 - Bz + zoff 2^48) mod 2^64; Bz = implicit bias of the lift bytes
+  uint32_t negM[4];      // -M mod 2^128
+  int64_t thr;           // capacity lift: |top 64 bits of R| above this means R is off by M
+  uint32_t khi_x, khi_c; // added to the top deposit word (exact / capacity)
+  uint32_t zhi;          // added to word 1 of the lift sum
   uint32_t zoff;         // multiple of M added to E so that zhat stays unsigned
-  uint32_t Bp5[5];       // Bp mod 2^160 (debug taps only)
+  float seed_x[32];      // Phase-A accumulator seeds per partial, exact lift
+  float seed_c[32];      // same, capacity lift
+  uint32_t Bp5[5];       // sum_s bits(seed_x[s]) 256^s mod 2^160 (debug taps only)
 };
 
 // Per-modulus constants of the residue arithmetic.

@@ -103,42 +103,86 @@ static void sub_words(uint32_t* a, const uint32_t* b, int nw) {
   }
 }
 
+// Splits delta (mod 2^bits) into per-slice seed offsets: bytes for slices
+// 0 .. n-2, 16 bits for slice n-1 (all < 2^16, so seed + P stays in one
+// binade); returns the remainder above bit 8 (n - 1) + 16.
+static u128 split_delta(u128 delta, int n, int* d) {
+  for (int s = 0; s < n; s++) {
+    int width = s < n - 1 ? 8 : 16;
+    d[s] = (int)((delta >> (8 * s)) & ((1u << width) - 1));
+  }
+  int top = 8 * (n - 1) + 16;
+  return top >= 128 ? 0 : (delta >> top) << top;
+}
+
 void build_crt_consts(const ModSet& H, CrtConsts& C) {
   memset(&C, 0, sizeof(C));
   C.r = H.r;
   C.S = H.S;
   C.T = H.T;
   C.nwords = (bitlen(H.M) + 2 <= 96) ? 3 : 4;
-  u128 M = H.M, Mh = H.M >> 1;
+  const int NW = C.nwords;
+  const u128 mask = NW == 4 ? ~(u128)0 : (((u128)1 << (32 * NW)) - 1);
+  u128 M = H.M, Mh = H.M >> 1, nM = (~H.M + 1);
   for (int i = 0; i < 4; i++) {
     C.M[i] = (uint32_t)(M >> (32 * i));
     C.Mhalf[i] = (uint32_t)(Mh >> (32 * i));
+    C.negM[i] = (uint32_t)(nM >> (32 * i));
   }
-  // Each Phase-A partial leaves the MFMA as the FP32 value 1.5 * 2^23 + P
-  // (the accumulator is seeded there; |P| < 2^22 holds for centred as well
-  // as canonical residues), whose bit pattern is 0x4B400000 + P.  The
-  // deposits therefore carry the implicit bias Bp = sum_s 0x4B400000 256^s
-  // and the lift bytes Bz = sum_t 0x4B400000 256^t.  Adding kLiftOffset M to
-  // E (and kLiftOffset 2^48 to the lift sum) keeps zhat unsigned for signed
-  // residues without changing R.
-  uint32_t Bp[5] = {0, 0, 0, 0, 0};
-  for (int s = 0; s < H.S; s++) add_shifted(Bp, 5, kFloatBiasBits, 8 * s);
-  memcpy(C.Bp5, Bp, sizeof(Bp));
-  uint32_t K0[5] = {C.Mhalf[0], C.Mhalf[1], C.Mhalf[2], C.Mhalf[3], 0};
-  sub_words(K0, Bp, 5);
-  u128 cm = H.M * (u128)kLiftOffset;
-  uint32_t CM[5] = {(uint32_t)cm, (uint32_t)(cm >> 32), (uint32_t)(cm >> 64), (uint32_t)(cm >> 96), 0};
-  uint64_t carry = 0;
-  for (int i = 0; i < 5; i++) {
-    uint64_t t = (uint64_t)K0[i] + CM[i] + carry;
-    K0[i] = (uint32_t)t;
-    carry = t >> 32;
-  }
-  for (int i = 0; i < 4; i++) C.K0[i] = K0[i];
-  uint64_t Bz = 0;
-  for (int t = 0; t < H.T; t++) Bz += (uint64_t)kFloatBiasBits << (8 * t);
-  C.Czh = ((uint64_t)1 << (kFracBits - 1)) - Bz + ((uint64_t)kLiftOffset << kFracBits);
+  // Capacity lift threshold on the top 64 bits of R: a quarter of M in those
+  // units.  A stage output satisfies |C| < 2^(cap - 1) far below it, a lift
+  // that is off by one multiple of M lands far above it.
+  C.thr = (int64_t)((M >> (32 * (NW - 2))) / 4);
   C.zoff = kLiftOffset;
+
+  // Bit patterns of the partials: bits(seed) + P with bits(seed) = kFloatBiasBits
+  // + delta.  The fast deposit adds pattern s at bit 8 s but drops the top
+  // byte (0x4B) of the pattern of every slice s = 4 c + 1 that lands at bit
+  // 32 c + 8; that constant is put back through the deltas.
+  const int S = H.S, T = H.T, VP = (S + 1) / 2;
+  u128 base = 0, dropped = 0;
+  for (int s = 0; s < S; s++) base += (u128)kFloatBiasBits << (8 * s);
+  for (int s = 1; s < S && 8 * s + 24 < 32 * NW; s += 4)
+    dropped += (u128)(kFloatBiasBits >> 24) << (8 * s + 24);
+  const u128 zM = H.M * (u128)kLiftOffset;
+  for (int variant = 0; variant < 2; variant++) {
+    // target: W = E + (exact ? M/2 : 0) + zoff M  (mod 2^(32 NW))
+    u128 want = (variant == 0 ? Mh : 0) + zM;
+    u128 delta = (want - base + dropped) & mask;
+    int d[16];
+    u128 rest = split_delta(delta, S, d);
+    // the remainder must sit inside the top word
+    if ((rest & (((u128)1 << (32 * (NW - 1))) - 1)) != 0) throw std::runtime_error("seed split");
+    uint32_t hi = (uint32_t)(rest >> (32 * (NW - 1)));
+    float* seed = variant == 0 ? C.seed_x : C.seed_c;
+    for (int j = 0; j < 32; j++) seed[j] = 12582912.0f;  // 1.5 * 2^23
+    for (int s2 = 0; s2 < S; s2++) seed[s2] = 12582912.0f + (float)d[s2];
+    if (variant == 0) C.khi_x = hi; else C.khi_c = hi;
+    if (variant == 0) {
+      // taps: the full (undropped) pattern sum of the seeds, mod 2^160
+      uint32_t Bp[5] = {0, 0, 0, 0, 0};
+      for (int s2 = 0; s2 < S; s2++) add_shifted(Bp, 5, kFloatBiasBits + (uint32_t)d[s2], 8 * s2);
+      memcpy(C.Bp5, Bp, sizeof(Bp));
+    }
+  }
+  // lift sum Z = sum_t bits(seed) 256^t (mod 2^64) + 2^47 (round half up) +
+  // zoff 2^48; only word 1 is read, and the fast sum drops the top byte of
+  // slice 1 (bit 32) as above
+  {
+    uint64_t zbase = 0, zdrop = 0;
+    for (int t = 0; t < T; t++) zbase += (uint64_t)kFloatBiasBits << (8 * t);
+    for (int t = 1; t < T && 8 * t + 24 < 64; t += 4) zdrop += (uint64_t)(kFloatBiasBits >> 24) << (8 * t + 24);
+    uint64_t want = ((uint64_t)1 << (kFracBits - 1)) + ((uint64_t)kLiftOffset << kFracBits);
+    uint64_t delta = want - zbase + zdrop;
+    int d[16];
+    u128 rest = split_delta((u128)delta, T, d) & (((u128)1 << 64) - 1);
+    if ((rest & 0xFFFFFFFFull) != 0) throw std::runtime_error("seed split");
+    C.zhi = (uint32_t)(rest >> 32);
+    for (int t = 0; t < T; t++) {
+      C.seed_x[2 * VP + t] = 12582912.0f + (float)d[t];
+      C.seed_c[2 * VP + t] = 12582912.0f + (float)d[t];
+    }
+  }
 }
 
 // ---- double-double trigonometry ----

@@ -1,0 +1,37 @@
+"""The autotuner: admissible factorisations (host) and a tuned plan's parity (GPU)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2606_23698_amd import inputs
+
+
+def test_admissible_splits():
+    from paper_2606_23698_amd.autotune import splits
+    assert splits(1024) == [(32, 32)]
+    assert splits(512) == [(16, 32), (32, 16)]
+    assert splits(96) == [(4, 24), (6, 16), (8, 12), (12, 8), (16, 6), (24, 4)]
+    assert splits(2) == []
+    for n in (32, 64, 96, 128, 192, 256, 384, 768):
+        for p, q in splits(n):
+            assert p * q == n and p % 2 == 0 and q % 2 == 0 and p <= 32 and q <= 32
+
+
+@pytest.mark.gpu
+def test_tuned_plan_is_bit_exact(gpu, tmp_path):
+    import torch
+    from oracle import exact as ox
+    from paper_2606_23698_amd import autotune
+    os.environ["OBFFT_AUTOTUNE_CACHE"] = str(tmp_path / "tune.json")
+    shape = (16, 96, 64)
+    best = autotune.tune(shape, reps=1)
+    assert best["substrate"] in ("fp16", "int8", "fp8")
+    again = autotune.tune(shape, reps=1)          # served from the cache
+    assert again == best
+    plan = autotune.tuned_plan(shape, reps=1)
+    x = inputs.uniform(shape, 21)
+    y = plan.forward(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    pq = tuple(tuple(v) for v in best["pq"])
+    ref = ox.fft3_exact(x, pq)
+    assert np.count_nonzero(y != ref) == 0

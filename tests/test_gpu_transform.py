@@ -98,6 +98,32 @@ def test_stage_residue_tap_matches_oracle_integers(gpu, substrate):
                 assert t2[line, slot, 1, k] == s2["im"][slot] % m
 
 
+@pytest.mark.parametrize("kind", ["max_corners", "max_tone"])
+def test_extreme_magnitudes_bit_exact(gpu, kind):
+    """Every column quantised to its largest magnitudes, so stage outputs
+    reach the capacity extreme (|C| near 2^109 .. 2^111: coherent sums of K
+    products of 53-bit data and 53-bit roots, Eq. capacity) where the lift
+    must still pick the right multiple of M."""
+    api = _api()
+    shape = (32, 16, 64)
+    a = 1.0 - 2.0 ** -53
+    if kind == "max_corners":
+        rng = np.random.default_rng(17)
+        x = (a * rng.choice([-1.0, 1.0], size=shape) + 1j * a * rng.choice([-1.0, 1.0], size=shape))
+    else:
+        n = [np.arange(m) for m in shape]
+        ph = (3 * n[0][:, None, None] / shape[0] + 5 * n[1][None, :, None] / shape[1]
+              + 7 * n[2][None, None, :] / shape[2])
+        x = a * np.exp(2j * np.pi * ph)
+    x = np.ascontiguousarray(x.astype(np.complex128))
+    plan = api.Plan(shape)
+    y = _run(plan, x, gpu)
+    ref = ox.fft3_exact(x, _pq(plan))
+    assert np.count_nonzero(y != ref) == 0
+    hi, lo = ox.fft3_dd(x)
+    assert rel_l2(y, hi, lo) <= 1e-14
+
+
 @pytest.mark.parametrize("substrate", ["fp16", "int8", "fp8"])
 def test_permuted_modulus_set_gives_identical_bits(gpu, substrate):
     """The reconstructed integers do not depend on the modulus order (any
