@@ -1,6 +1,6 @@
 """Autotuner: per shape, the six-step factorisation and the MFMA substrate.
 
-Candidates per axis are the admissible splits N = p q (both even, both <= 32;
+Candidates per axis are the admissible splits N = p q (both <= 32;
 p <= q and p > q are different plans with different output bits, as the
 factorisation fixes which roundings happen where); candidates for the
 substrate are FP16, INT8 and FP8 (bit-identical outputs for one
@@ -23,10 +23,10 @@ MAX_K = 32
 
 def splits(N):
     out = []
-    for p in range(2, MAX_K + 1, 2):
+    for p in range(1, MAX_K + 1):
         if N % p == 0:
             q = N // p
-            if q % 2 == 0 and 2 <= q <= MAX_K:
+            if 1 <= q <= MAX_K:
                 out.append((p, q))
     return out
 

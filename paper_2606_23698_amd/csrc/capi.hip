@@ -94,20 +94,27 @@ extern "C" void obfft_options_default(obfft_options_t* opt) {
   opt->substrate = OBFFT_SUB_AUTO;
 }
 
-// Library default factorisation N = p q: p <= q, both even, both <= 32,
-// p as close to sqrt(N) as possible (32 = 4 x 8, 256 = 16 x 16, 1024 = 32 x 32).
+// Library default factorisation N = p q with p <= q <= 32: the most balanced
+// split with both factors even if there is one (32 = 4 x 8, 256 = 16 x 16,
+// 1024 = 32 x 32, 12 = 2 x 6), else the most balanced split of any parity
+// (9 = 3 x 3, 18 = 3 x 6, 1 = 1 x 1: a length-1 axis is an exact identity).
 static bool default_split(int64_t N, int* p, int* q) {
-  int best = -1;
-  for (int a = 2; a <= kMaxK; a += 2) {
-    if (N % a) continue;
-    int64_t b = N / a;
-    if (b < a || b > kMaxK || (b & 1)) continue;
-    best = a;
+  for (int pass = 0; pass < 2; pass++) {
+    int best = -1;
+    for (int a = 1; a <= kMaxK; a++) {
+      if (N % a) continue;
+      int64_t b = N / a;
+      if (b < a || b > kMaxK) continue;
+      if (pass == 0 && ((a & 1) || (b & 1))) continue;
+      best = a;
+    }
+    if (best > 0) {
+      *p = best;
+      *q = (int)(N / best);
+      return true;
+    }
   }
-  if (best < 0) return false;
-  *p = best;
-  *q = (int)(N / best);
-  return true;
+  return false;
 }
 
 static void build_modconsts(const ModSet& H, ModConsts& MC, int substrate) {
@@ -161,7 +168,7 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
     } else if ((int64_t)pp * qq != N) {
       return OBFFT_INVALID_VALUE;
     }
-    if (pp < 2 || qq < 2 || (pp & 1) || (qq & 1) || pp > kMaxK || qq > kMaxK) return OBFFT_UNSUPPORTED_SIZE;
+    if (pp < 1 || qq < 1 || pp > kMaxK || qq > kMaxK) return OBFFT_UNSUPPORTED_SIZE;
     plan->p[a] = pp;
     plan->q[a] = qq;
     kmax = std::max<int64_t>(kmax, std::max(pp, qq));

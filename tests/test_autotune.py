@@ -11,11 +11,12 @@ def test_admissible_splits():
     from paper_2606_23698_amd.autotune import splits
     assert splits(1024) == [(32, 32)]
     assert splits(512) == [(16, 32), (32, 16)]
-    assert splits(96) == [(4, 24), (6, 16), (8, 12), (12, 8), (16, 6), (24, 4)]
-    assert splits(2) == []
-    for n in (32, 64, 96, 128, 192, 256, 384, 768):
+    assert splits(96) == [(3, 32), (4, 24), (6, 16), (8, 12), (12, 8), (16, 6), (24, 4), (32, 3)]
+    assert splits(1) == [(1, 1)]
+    assert splits(37) == []
+    for n in (1, 9, 32, 64, 96, 128, 192, 256, 384, 768):
         for p, q in splits(n):
-            assert p * q == n and p % 2 == 0 and q % 2 == 0 and p <= 32 and q <= 32
+            assert p * q == n and 1 <= p <= 32 and 1 <= q <= 32
 
 
 @pytest.mark.gpu

@@ -53,6 +53,11 @@ def test_forward_32cubed_bit_exact(gpu, substrate):
     ((16, 8, 32), ((4, 4), (2, 4), (8, 4))),
     ((4, 64, 24), None),
     ((32, 16, 64), ((8, 4), (4, 4), (8, 8))),
+    ((1, 9, 32), None),                       # length-1 axis, odd 3 x 3
+    ((15, 1, 25), None),                      # 3 x 5 and 5 x 5
+    ((3, 5, 7), None),                        # 1 x 3, 1 x 5, 1 x 7
+    ((1, 1, 1), None),                        # the identity
+    ((18, 4, 2), ((3, 6), (1, 4), (2, 1))),   # forced odd / unit factors
 ])
 @pytest.mark.parametrize("substrate", ["fp8", "fp16"])
 def test_forward_small_shapes_bit_exact(gpu, shape, pq, substrate):

@@ -62,7 +62,7 @@ def test_capacity_budget_rejects_rev33():
 def test_unsupported_and_invalid_sizes():
     from paper_2606_23698_amd import api
     from paper_2606_23698_amd._lib import ObfftError
-    for shape, status in [((2, 32, 32), 2), ((1030, 32, 32), 2), ((32, 32, 66), 2)]:
+    for shape, status in [((37, 32, 32), 2), ((1030, 32, 32), 2), ((32, 32, 74), 2), ((32, 0, 32), 1)]:
         with pytest.raises(ObfftError) as e:
             api.Plan(shape)
         assert e.value.status == status, shape
