@@ -206,6 +206,7 @@ obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
  * in a hipGraph and replayed.  Members with equal shapes share one plan.
  * Outputs are bit-identical to fft3d_z2z_forward on each member.  The batch
  * owns a workspace of the summed member sizes, allocated on first use.
+ * 1 <= count <= 65535, else OBFFT_INVALID_VALUE.
  * ins/outs: host arrays of `count` device pointers. */
 obfft_status_t obfft_batch_plan_create(obfft_plan_t* plan, int count, const int64_t* shapes,
                                        const obfft_options_t* opt);

@@ -13,16 +13,17 @@
 #include "plan_math.h"
 
 namespace obfft {
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                        int64_t grid, hipStream_t st);
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, int64_t grid, hipStream_t st);
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
-                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts& C, hipStream_t st);
+                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
 int stage_cols_per_wg(int K);
-hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* prefix, int ndesc,
-                        int64_t grid, const ModConsts& MC, const CrtConsts& C, hipStream_t st);
+hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* first,
+                        const uint16_t* tmember, int64_t total, hipStream_t st);
+int kclass_of(int K);
+int kclass_kmax(int c);
 struct NativePlan;
 NativePlan* native_plan_create(const int64_t* n, std::string& err);
 void native_plan_destroy(NativePlan* np);
@@ -49,6 +50,8 @@ struct obfft_plan_s {
   DevPlanes planes[3][2][2];  // axis, stage-1, direction
   std::vector<void*> dev_allocs;
   uint16_t* d_phaseA = nullptr;
+  const ModConsts* d_mc = nullptr;    // device copies of MC and C
+  const CrtConsts* d_crt = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
@@ -59,18 +62,18 @@ struct obfft_plan_s {
   int batch_count = 0;
   std::vector<obfft_plan_t> members;          // owned, one per distinct shape
   std::vector<obfft_plan_t> members_of_batch; // per batch entry (borrowed)
-  int batch_kmax = 0;
   StageParams* d_desc = nullptr;      // device [6][count]
   StageParams* h_desc = nullptr;      // pinned host staging [6][count]
-  int64_t* d_prefix = nullptr;        // device [6][count + 1]
-  int64_t batch_total[6] = {0, 0, 0, 0, 0, 0};
+  int64_t* d_first = nullptr;         // device [6][count]: a member's first tile in its class launch
+  uint16_t* d_tmember = nullptr;      // device: member of every tile, launches concatenated
+  int64_t tmember_off[6][5] = {};     // per pass and K class: offset into d_tmember
+  int64_t batch_total[6][5] = {};     // per pass and K class: tiles (= grid of that launch)
   void* batch_ws = nullptr;
   std::vector<size_t> ws_off;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t capture_stream = nullptr;
   hipEvent_t desc_done = nullptr;     // the last descriptor upload has left the pinned buffer
-  int64_t batch_grid[6] = {0, 0, 0, 0, 0, 0};
   bool use_graph = true;
 };
 
@@ -215,6 +218,14 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   obfft_status_t s = upload(plan, pa.data(), pa.size() * 2, &dpa);
   if (s != OBFFT_SUCCESS) return s;
   plan->d_phaseA = (uint16_t*)dpa;
+  void* dmc = nullptr;
+  void* dcr = nullptr;
+  s = upload(plan, &plan->MC, sizeof(ModConsts), &dmc);
+  if (s != OBFFT_SUCCESS) return s;
+  s = upload(plan, &plan->C, sizeof(CrtConsts), &dcr);
+  if (s != OBFFT_SUCCESS) return s;
+  plan->d_mc = (const ModConsts*)dmc;
+  plan->d_crt = (const CrtConsts*)dcr;
   plan->ws_bytes = (size_t)(plan->n[0] * plan->n[1] * plan->n[2]) * (plan->precision ? 8 : 16);
   if (hipDeviceSynchronize() != hipSuccess) return OBFFT_HIP_ERROR;
   if (plan->precision == OBFFT_PREC_FP64) {
@@ -261,7 +272,8 @@ extern "C" obfft_status_t obfft_plan_destroy(obfft_plan_t plan) {
   if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
   if (plan->desc_done) (void)hipEventDestroy(plan->desc_done);
   if (plan->d_desc) (void)hipFree(plan->d_desc);
-  if (plan->d_prefix) (void)hipFree(plan->d_prefix);
+  if (plan->d_first) (void)hipFree(plan->d_first);
+  if (plan->d_tmember) (void)hipFree(plan->d_tmember);
   if (plan->h_desc) (void)hipHostFree(plan->h_desc);
   if (plan->batch_ws) (void)hipFree(plan->batch_ws);
   for (void* d : plan->dev_allocs) hipFree(d);
@@ -347,6 +359,8 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   P.amat_chmax = L.chmax;
   P.amat_mt = L.mt;
   P.phaseA = plan->d_phaseA;
+  P.mc = plan->d_mc;
+  P.crt = plan->d_crt;
   if (stage == 1) {
     P.K = (int)q;
     P.G = (int)p;
@@ -379,7 +393,7 @@ static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int dire
   P.extra_shift = extra_shift;
   P.dbg_res = dbg;
   if (grid <= 0) return OBFFT_SUCCESS;
-  if (launch_stage(plan->substrate, plan->precision, P, plan->MC, plan->C, grid, st) != hipSuccess)
+  if (launch_stage(plan->substrate, plan->precision, P, grid, st) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;
 }
@@ -484,6 +498,7 @@ struct CrtCache {
   bool ready = false;
   CrtConsts C;
   uint16_t* d_phaseA = nullptr;
+  CrtConsts* d_C = nullptr;
 };
 static std::mutex g_crt_mu;
 static std::map<std::pair<int, int>, CrtCache> g_crt;
@@ -511,11 +526,14 @@ extern "C" obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const 
       if (hipMalloc(&cc->d_phaseA, pa.size() * 2) != hipSuccess) return OBFFT_ALLOC_FAILED;
       if (hipMemcpy(cc->d_phaseA, pa.data(), pa.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
         return OBFFT_HIP_ERROR;
+      if (hipMalloc(&cc->d_C, sizeof(CrtConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
+      if (hipMemcpy(cc->d_C, &cc->C, sizeof(CrtConsts), hipMemcpyHostToDevice) != hipSuccess)
+        return OBFFT_HIP_ERROR;
       cc->ready = true;
     }
   }
   if (launch_crt(precision, n, (const uint16_t*)residues, (const int*)exps, out, (uint32_t*)taps, cc->d_phaseA,
-                 cc->C, (hipStream_t)stream) != hipSuccess)
+                 cc->d_C, (hipStream_t)stream) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;
 }
@@ -544,17 +562,18 @@ extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* 
 // ---- batched transforms ----
 //
 // All member transforms of a batch run pass by pass (axis n3 stage 1, n3
-// stage 2, n2 ..., n1 stage 2): each pass is ONE launch over the tiles of
-// every member (a workgroup per tile), driven by a device table of stage
-// descriptors.  The
-// six launches are captured once in a hipGraph and replayed; only the table
-// (with the callers' pointers) is re-uploaded per call.
+// stage 2, n2 ..., n1 stage 2).  In every pass the members are grouped by the
+// contraction length K of their stage (K <= 4, 8, 12, 16, 32: the kernel's
+// compile-time tile shape), and each group is ONE launch over the tiles of
+// all its members (a workgroup per tile), driven by a device table of stage
+// descriptors.  The launches are captured once in a hipGraph and replayed;
+// only the table (with the callers' pointers) is re-uploaded per call.
 static const int kPassAxis[6] = {2, 2, 1, 1, 0, 0};
 static const int kPassStage[6] = {1, 2, 1, 2, 1, 2};
 
 extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
                                                   const obfft_options_t* opt) {
-  if (!out || count <= 0 || !shapes) return OBFFT_INVALID_VALUE;
+  if (!out || count <= 0 || count > 65535 || !shapes) return OBFFT_INVALID_VALUE;
   *out = nullptr;
   obfft_options_t def;
   obfft_options_default(&def);
@@ -585,11 +604,6 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
   bp->precision = OBFFT_PREC_FP64;
   bp->MC = per[0]->MC;
   bp->C = per[0]->C;
-  int kmax = 0;
-  for (int i = 0; i < count; i++)
-    for (int a = 0; a < 3; a++) kmax = std::max(kmax, std::max(per[i]->p[a], per[i]->q[a]));
-  bp->batch_kmax = kmax <= 16 ? 16 : 32;
-  const int ncol = stage_cols_per_wg(bp->batch_kmax);
   // workspace offsets (256-byte aligned)
   size_t off = 0;
   bp->ws_off.resize(count);
@@ -598,42 +612,56 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     off += (per[i]->ws_bytes + 255) & ~(size_t)255;
   }
   bp->ws_bytes = off;
-  // descriptors without pointers, prefix sums of tiles
+  // descriptors without pointers; per pass and K class, the members' tiles
   size_t dbytes = sizeof(StageParams) * 6 * count;
   if (hipHostMalloc((void**)&bp->h_desc, dbytes, hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&bp->d_desc, dbytes) != hipSuccess ||
-      hipMalloc((void**)&bp->d_prefix, sizeof(int64_t) * 6 * (count + 1)) != hipSuccess) {
+      hipMalloc((void**)&bp->d_first, sizeof(int64_t) * 6 * count) != hipSuccess) {
     obfft_plan_destroy(bp);
     return OBFFT_ALLOC_FAILED;
   }
-  std::vector<int64_t> prefix(6 * (count + 1));
+  std::vector<int64_t> first(6 * count), tiles(6 * count);
+  std::vector<int> cls(6 * count);
   for (int pass = 0; pass < 6; pass++) {
-    int64_t acc = 0;
     for (int i = 0; i < count; i++) {
       StageParams& P = bp->h_desc[pass * count + i];
       int64_t grid;
       stage_params(per[i], kPassAxis[pass], kPassStage[pass], 0, nullptr, nullptr, P, grid);
-      // tiles on the batch kernel's shape
-      if (P.stage == 1) {
-        grid = (P.ncols + ncol - 1) / ncol;
-      } else {
-        P.tiles_per_g = (int)((P.ncols + ncol - 1) / ncol);
-        grid = (int64_t)P.tiles_per_g * P.G;
-      }
-      prefix[pass * (count + 1) + i] = acc;
-      acc += grid;
+      cls[pass * count + i] = kclass_of(P.K);
+      tiles[pass * count + i] = grid;  // the single-transform tiling is the class's
     }
-    prefix[pass * (count + 1) + count] = acc;
-    bp->batch_total[pass] = acc;
+    for (int c = 0; c < 5; c++) {
+      int64_t acc = 0;
+      for (int i = 0; i < count; i++) {
+        if (cls[pass * count + i] != c) continue;
+        first[pass * count + i] = acc;
+        acc += tiles[pass * count + i];
+      }
+      bp->batch_total[pass][c] = acc;
+    }
   }
-  if (hipMemcpy(bp->d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice) !=
-      hipSuccess || hipEventCreateWithFlags(&bp->desc_done, hipEventDisableTiming) != hipSuccess) {
+  int64_t ttot = 0;
+  for (int pass = 0; pass < 6; pass++)
+    for (int c = 0; c < 5; c++) {
+      bp->tmember_off[pass][c] = ttot;
+      ttot += bp->batch_total[pass][c];
+    }
+  std::vector<uint16_t> tm((size_t)std::max<int64_t>(ttot, 1));
+  for (int pass = 0; pass < 6; pass++)
+    for (int i = 0; i < count; i++) {
+      int64_t base = bp->tmember_off[pass][cls[pass * count + i]] + first[pass * count + i];
+      for (int64_t t = 0; t < tiles[pass * count + i]; t++) tm[base + t] = (uint16_t)i;
+    }
+  if (hipMalloc((void**)&bp->d_tmember, tm.size() * sizeof(uint16_t)) != hipSuccess) {
+    obfft_plan_destroy(bp);
+    return OBFFT_ALLOC_FAILED;
+  }
+  if (hipMemcpy(bp->d_first, first.data(), sizeof(int64_t) * first.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bp->d_tmember, tm.data(), tm.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&bp->desc_done, hipEventDisableTiming) != hipSuccess) {
     obfft_plan_destroy(bp);
     return OBFFT_HIP_ERROR;
   }
-  // one workgroup per tile: the hardware dispatcher balances the uneven
-  // members, and no loop state stays live across tiles
-  for (int pass = 0; pass < 6; pass++) bp->batch_grid[pass] = bp->batch_total[pass];
   bp->members_of_batch = per;
   *out = bp;
   return OBFFT_SUCCESS;
@@ -641,13 +669,14 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
 
 static obfft_status_t batch_launch_passes(obfft_plan_t bp, hipStream_t st) {
   int count = bp->batch_count;
-  for (int pass = 0; pass < 6; pass++) {
-    int64_t grid = bp->batch_grid[pass];
-    if (grid <= 0) continue;
-    if (launch_batch(bp->substrate, bp->batch_kmax, bp->d_desc + pass * count, bp->d_prefix + pass * (count + 1),
-                     count, grid, bp->MC, bp->C, st) != hipSuccess)
-      return OBFFT_HIP_ERROR;
-  }
+  for (int pass = 0; pass < 6; pass++)
+    for (int c = 0; c < 5; c++) {
+      int64_t total = bp->batch_total[pass][c];
+      if (total <= 0) continue;
+      if (launch_batch(bp->substrate, kclass_kmax(c), bp->d_desc + pass * count, bp->d_first + pass * count,
+                       bp->d_tmember + bp->tmember_off[pass][c], total, st) != hipSuccess)
+        return OBFFT_HIP_ERROR;
+    }
   return OBFFT_SUCCESS;
 }
 

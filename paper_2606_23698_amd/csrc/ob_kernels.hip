@@ -222,12 +222,19 @@ __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, const v16f& see
 }
 
 // Accumulator seeds of the Phase-A MFMA: register v of lane half h holds
-// partial 2v + h, seeded with tbl[2v + h] (1.5 * 2^23 plus the folded lift
+// partial 2v + h, seeded with tbl[h][v] (1.5 * 2^23 plus the folded lift
 // constants of that slice).
-__device__ __forceinline__ v16f phase_a_seed(const float* tbl, int h) {
+__device__ __forceinline__ v16f phase_a_seed(const float (*tbl)[16], int h) {
   v16f c;
+  const float4* row = (const float4*)tbl[h];
 #pragma unroll
-  for (int v = 0; v < 16; v++) c[v] = h ? tbl[2 * v + 1] : tbl[2 * v];
+  for (int q = 0; q < 4; q++) {
+    const float4 f = row[q];
+    c[4 * q] = f.x;
+    c[4 * q + 1] = f.y;
+    c[4 * q + 2] = f.z;
+    c[4 * q + 3] = f.w;
+  }
   // opaque to the optimiser: the seed stays resident in 16 VGPRs instead of
   // being rematerialised before every MFMA
   asm volatile("" : "+v"(c));
@@ -240,8 +247,7 @@ __device__ __forceinline__ v16f phase_a_seed(const float* tbl, int h) {
 extern __shared__ __align__(16) unsigned char smem[];
 
 template <int SUB, int TGT, int KMAX>
-__device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                                           int64_t tile) {
+__device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
@@ -341,6 +347,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
 #pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
+    const ModConsts& MC = *P.mc;
     const double md = (double)MC.m[i], imd = MC.inv_md[i];
     const float mf = (float)MC.m[i], imf = MC.inv_mf[i];
     const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
@@ -525,7 +532,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
   // high half moduli ML .. r-1; one swap per packed pair hands each half the
   // other half's share (b1: the low lanes' outputs, b2: the high lanes').
   const v8h aop = *(const v8h*)(P.phaseA + lane * 8);
-  const v16f seed = phase_a_seed(C.seed_c, lane >> 5);
+  const CrtConsts& C = *P.crt;
+  const v16f seed = phase_a_seed(C.seedT_c, lane >> 5);
   const int64_t co = col_out[col];
   const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
   typename TT::T re_part = 0;
@@ -571,36 +579,30 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, const ModConsts
 }
 
 template <int SUB, int TGT, int KMAX>
-__global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P, const ModConsts MC,
-                                                            const CrtConsts C) {
-  stage_tile<SUB, TGT, KMAX>(P, MC, C, (int64_t)blockIdx.x);
+__global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P) {
+  stage_tile<SUB, TGT, KMAX>(P, (int64_t)blockIdx.x);
 }
 
-// Batched stage: one workgroup per tile of all transforms of one Bailey
-// pass.  descs[d] describes transform d's stage and prefix[d] is the index
-// of its first tile (prefix[ndesc] = total tiles = the grid).
+// Batched stage: one workgroup per tile of the members of one Bailey pass
+// whose contraction length falls in this kernel's class.  tmember[t] is the
+// member that owns tile t, descs[d] its stage and first[d] its first tile.
 template <int SUB, int TGT, int KMAX>
-__global__ __launch_bounds__(kThreads) void ob_batch_kernel(const StageParams* __restrict__ descs,
-                                                            const int64_t* __restrict__ prefix, int ndesc,
-                                                            const ModConsts MC, const CrtConsts C) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
+                                                            const int64_t* __restrict__ first,
+                                                            const uint16_t* __restrict__ tmember, int64_t total) {
   const int64_t t = blockIdx.x;
-  if (t >= prefix[ndesc]) return;
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads become scalar
-  const StageParams P = descs[lo];
-  stage_tile<SUB, TGT, KMAX>(P, MC, C, t - prefix[lo]);
+  if (t >= total) return;
+  const int d = __builtin_amdgcn_readfirstlane((int)tmember[t]);  // uniform: scalar descriptor loads
+  const StageParams P = descs[d];
+  stage_tile<SUB, TGT, KMAX>(P, t - first[d]);
 }
 
 // ---- standalone CRT reconstruction (unit-level access to Phase A / B) ----
 template <int TGT>
 __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* residues, const int* exps,
                                                   void* out, uint32_t* taps, const uint16_t* phaseA,
-                                                  const CrtConsts C) {
+                                                  const CrtConsts* crt) {
+  const CrtConsts& C = *crt;
   typedef Tgt<TGT> TT;
   constexpr int R = TT::R;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
     b2[j] = (use && o2 < n) ? (_Float16)(float)residues[o2 * R + k] : (_Float16)0.0f;
   }
   float xv[EP::NV], yv[EP::NV];
-  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(C.seed_x, h), xv, yv);
+  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(C.seedT_x, h), xv, yv);
   uint32_t wv[TT::NW];
   EP::deposits(xv, yv, C.khi_x, wv);
   const uint32_t zh = EP::zhat(xv, yv, C.zhi);
@@ -697,8 +699,7 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
 
 // ---- host-side launch helpers ----
 template <int SUB, int TGT, int KMAX>
-static hipError_t launch_stage_t(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                                 int64_t grid, hipStream_t st) {
+static hipError_t launch_stage_t(const StageParams& P, int64_t grid, hipStream_t st) {
   int lds = StageLds<SUB, TGT, KMAX>::bytes(P.K);
   static bool attr_set = false;
   if (!attr_set) {
@@ -707,37 +708,34 @@ static hipError_t launch_stage_t(const StageParams& P, const ModConsts& MC, cons
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, P,
-                     MC, C);
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, P);
   return hipGetLastError();
 }
 
 template <int SUB, int TGT>
-static hipError_t launch_stage_k(const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                                 int64_t grid, hipStream_t st) {
+static hipError_t launch_stage_k(const StageParams& P, int64_t grid, hipStream_t st) {
   int K = P.K;
-  if (K <= 4) return launch_stage_t<SUB, TGT, 4>(P, MC, C, grid, st);
-  if (K <= 8) return launch_stage_t<SUB, TGT, 8>(P, MC, C, grid, st);
-  if (K <= 12) return launch_stage_t<SUB, TGT, 12>(P, MC, C, grid, st);
-  if (K <= 16) return launch_stage_t<SUB, TGT, 16>(P, MC, C, grid, st);
-  return launch_stage_t<SUB, TGT, 32>(P, MC, C, grid, st);
+  if (K <= 4) return launch_stage_t<SUB, TGT, 4>(P, grid, st);
+  if (K <= 8) return launch_stage_t<SUB, TGT, 8>(P, grid, st);
+  if (K <= 12) return launch_stage_t<SUB, TGT, 12>(P, grid, st);
+  if (K <= 16) return launch_stage_t<SUB, TGT, 16>(P, grid, st);
+  return launch_stage_t<SUB, TGT, 32>(P, grid, st);
 }
 
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, const ModConsts& MC, const CrtConsts& C,
-                        int64_t grid, hipStream_t st) {
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, int64_t grid, hipStream_t st) {
   if (sub == SUB_FP16)
-    return tgt == 0 ? launch_stage_k<SUB_FP16, 0>(P, MC, C, grid, st)
-                    : launch_stage_k<SUB_FP16, 1>(P, MC, C, grid, st);
+    return tgt == 0 ? launch_stage_k<SUB_FP16, 0>(P, grid, st)
+                    : launch_stage_k<SUB_FP16, 1>(P, grid, st);
   if (sub == SUB_INT8)
-    return tgt == 0 ? launch_stage_k<SUB_INT8, 0>(P, MC, C, grid, st)
-                    : launch_stage_k<SUB_INT8, 1>(P, MC, C, grid, st);
-  return tgt == 0 ? launch_stage_k<SUB_FP8, 0>(P, MC, C, grid, st)
-                  : launch_stage_k<SUB_FP8, 1>(P, MC, C, grid, st);
+    return tgt == 0 ? launch_stage_k<SUB_INT8, 0>(P, grid, st)
+                    : launch_stage_k<SUB_INT8, 1>(P, grid, st);
+  return tgt == 0 ? launch_stage_k<SUB_FP8, 0>(P, grid, st)
+                  : launch_stage_k<SUB_FP8, 1>(P, grid, st);
 }
 
 template <int SUB, int KMAX>
-static hipError_t launch_batch_t(const StageParams* descs, const int64_t* prefix, int ndesc, int64_t grid,
-                                 const ModConsts& MC, const CrtConsts& C, hipStream_t st) {
+static hipError_t launch_batch_t(const StageParams* descs, const int64_t* first, const uint16_t* tmember,
+                                 int64_t total, hipStream_t st) {
   int lds = StageLds<SUB, 0, KMAX>::bytes(KMAX);
   static bool attr_set = false;
   if (!attr_set) {
@@ -746,29 +744,44 @@ static hipError_t launch_batch_t(const StageParams* descs, const int64_t* prefix
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, descs, prefix,
-                     ndesc, MC, C);
+  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX>), dim3((unsigned)total), dim3(kThreads), lds, st, descs, first,
+                     tmember, total);
   return hipGetLastError();
 }
 
-// FP64-target batched pass; kmax <= 16 uses the 64-column shape, else 32.
-hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* prefix, int ndesc,
-                        int64_t grid, const ModConsts& MC, const CrtConsts& C, hipStream_t st) {
-  if (sub == SUB_FP16)
-    return kmax <= 16 ? launch_batch_t<SUB_FP16, 16>(descs, prefix, ndesc, grid, MC, C, st)
-                      : launch_batch_t<SUB_FP16, 32>(descs, prefix, ndesc, grid, MC, C, st);
-  if (sub == SUB_INT8)
-    return kmax <= 16 ? launch_batch_t<SUB_INT8, 16>(descs, prefix, ndesc, grid, MC, C, st)
-                      : launch_batch_t<SUB_INT8, 32>(descs, prefix, ndesc, grid, MC, C, st);
-  return kmax <= 16 ? launch_batch_t<SUB_FP8, 16>(descs, prefix, ndesc, grid, MC, C, st)
-                    : launch_batch_t<SUB_FP8, 32>(descs, prefix, ndesc, grid, MC, C, st);
+// K classes of the batched launches: the stage kernel's compile-time tile
+// shapes (K <= 4, 8, 12, 16, 32).
+int kclass_of(int K) { return K <= 4 ? 0 : K <= 8 ? 1 : K <= 12 ? 2 : K <= 16 ? 3 : 4; }
+int kclass_kmax(int c) {
+  static const int kmax[5] = {4, 8, 12, 16, 32};
+  return kmax[c];
+}
+
+template <int SUB>
+static hipError_t launch_batch_s(int kmax, const StageParams* descs, const int64_t* first, const uint16_t* tmember,
+                                 int64_t total, hipStream_t st) {
+  switch (kmax) {
+    case 4: return launch_batch_t<SUB, 4>(descs, first, tmember, total, st);
+    case 8: return launch_batch_t<SUB, 8>(descs, first, tmember, total, st);
+    case 12: return launch_batch_t<SUB, 12>(descs, first, tmember, total, st);
+    case 16: return launch_batch_t<SUB, 16>(descs, first, tmember, total, st);
+    default: return launch_batch_t<SUB, 32>(descs, first, tmember, total, st);
+  }
+}
+
+// FP64-target batched launch over the members of one pass and K class.
+hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* first, const uint16_t* tmember,
+                        int64_t total, hipStream_t st) {
+  if (sub == SUB_FP16) return launch_batch_s<SUB_FP16>(kmax, descs, first, tmember, total, st);
+  if (sub == SUB_INT8) return launch_batch_s<SUB_INT8>(kmax, descs, first, tmember, total, st);
+  return launch_batch_s<SUB_FP8>(kmax, descs, first, tmember, total, st);
 }
 
 // Columns per workgroup of the stage kernel for contraction length K.
 int stage_cols_per_wg(int K) { return K <= 16 ? Shape<16>::NCOL : Shape<32>::NCOL; }
 
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
-                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts& C, hipStream_t st) {
+                      uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   if (tgt == 0)
     hipLaunchKernelGGL(crt_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, n, residues, exps, out, taps,

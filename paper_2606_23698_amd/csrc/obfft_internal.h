@@ -46,6 +46,8 @@ struct CrtConsts {
   uint32_t zoff;         // multiple of M added to E so that zhat stays unsigned
   float seed_x[32];      // Phase-A accumulator seeds per partial, exact lift
   float seed_c[32];      // same, capacity lift
+  float seedT_x[2][16];  // seed_x[2 v + h] at [h][v]: one lane half's registers
+  float seedT_c[2][16];  // same for seed_c
   uint32_t Bp5[5];       // sum_s bits(seed_x[s]) 256^s mod 2^160 (debug taps only)
 };
 
@@ -78,6 +80,8 @@ struct StageParams {
   int64_t amat_mod_stride;  // bytes per modulus
   const uint16_t* phaseA;   // 64 lanes x 8 FP16 operand of the Phase-A MFMA
   uint16_t* dbg_res;        // canonical residues tap (may be null)
+  const ModConsts* mc;      // device copies of the plan constants (read per use,
+  const CrtConsts* crt;     // so that they do not occupy scalar registers)
 };
 
 // Plan-time per-(N, p, q) operand set for one stage direction.

@@ -165,6 +165,7 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
       memcpy(C.Bp5, Bp, sizeof(Bp));
     }
   }
+  // (the transposed copies are filled after the lift-sum seeds below)
   // lift sum Z = sum_t bits(seed) 256^t (mod 2^64) + 2^47 (round half up) +
   // zoff 2^48; only word 1 is read, and the fast sum drops the top byte of
   // slice 1 (bit 32) as above
@@ -183,6 +184,11 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
       C.seed_c[2 * VP + t] = 12582912.0f + (float)d[t];
     }
   }
+  for (int h = 0; h < 2; h++)
+    for (int v = 0; v < 16; v++) {
+      C.seedT_x[h][v] = C.seed_x[2 * v + h];
+      C.seedT_c[h][v] = C.seed_c[2 * v + h];
+    }
 }
 
 // ---- double-double trigonometry ----
