@@ -199,6 +199,7 @@ def main():
     if args.stage_reps > 0:
         ws_a = torch.empty_like(x)
         stage_ms, durs = stage_durations(plan, x, y, ws_a, args.stage_reps)
+        print("[bench] stage launches (ms): " + " ".join(f"{d:.2f}" for d in durs), file=sys.stderr, flush=True)
         del ws_a
     torch.cuda.synchronize()
 

@@ -381,6 +381,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     P.s_out_t = q * inner;
     int ncw = stage_cols_per_wg(P.K);
     P.tiles_per_g = (int)((P.ncols + ncw - 1) / ncw);
+    P.g_minor = inner == 1;
     grid = (int64_t)P.tiles_per_g * q;
   }
 }

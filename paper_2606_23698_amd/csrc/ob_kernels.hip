@@ -269,9 +269,27 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   int64_t g = 0, cstart;
   if (P.stage == 1) {
     cstart = tile * NCOL;
-  } else {
+  } else if (!P.g_minor) {
     g = tile / P.tiles_per_g;
     cstart = (tile % P.tiles_per_g) * NCOL;
+  } else {
+    // Contiguous axis: a stage-2 tile writes 16 bytes per output row at a
+    // stride of q elements, so the G tiles of one column tile (one per k2)
+    // together fill whole cache lines.  Workgroups go to the 8 XCDs round
+    // robin (workgroup b on XCD b % 8), each with its own L2: give XCD x the
+    // column tiles c = 8 j + x and run all G groups of one column tile on it
+    // back to back, so that the partial lines merge in that L2.
+    const int64_t T = P.tiles_per_g, G = P.G;
+    int64_t c;
+    if ((T & 7) == 0) {
+      const int64_t x = tile & 7, slot = tile >> 3;
+      g = slot % G;
+      c = (slot / G) * 8 + x;
+    } else {
+      g = tile % G;
+      c = tile / G;
+    }
+    cstart = c * NCOL;
   }
   if (tid < NCOL) {
     int64_t c = cstart + tid;

@@ -73,6 +73,8 @@ struct StageParams {
   int G;                // number of column groups (p for stage 1, q for stage 2)
   int stage;
   int tiles_per_g;      // stage 2 only
+  int g_minor;          // stage 2: tile order (0: group-major; 1: all groups of a
+                        // column tile on one XCD back to back, see stage_tile)
   int extra_shift;      // added to the pack exponent
   const uint8_t* amat;  // MFMA A-operand planes of this stage / direction
   int64_t amat_g_stride;  // bytes per group g (0 for stage 1)
