@@ -274,20 +274,25 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
     cstart = (tile % P.tiles_per_g) * NCOL;
   } else {
     // Contiguous axis: a stage-2 tile writes 16 bytes per output row at a
-    // stride of q elements, so the G tiles of one column tile (one per k2)
-    // together fill whole cache lines.  Workgroups go to the 8 XCDs round
-    // robin (workgroup b on XCD b % 8), each with its own L2: give XCD x the
-    // column tiles c = 8 j + x and run all G groups of one column tile on it
-    // back to back, so that the partial lines merge in that L2.
+    // stride of q elements; the 8 tiles of one column tile with k2 = 8b ..
+    // 8b + 7 together fill whole 128-byte lines.  Workgroups go to the 8 XCDs
+    // round robin (workgroup w on XCD w % 8), each with its own L2: XCD x
+    // takes the column tiles c = 8 j + x, and for one block of 8 groups at a
+    // time runs the 8 groups of a column tile back to back, so that the
+    // partial lines merge in that L2 while only 8 groups' matrix planes are
+    // live in it.
     const int64_t T = P.tiles_per_g, G = P.G;
+    const int64_t GB = (G & 7) == 0 ? 8 : G;
     int64_t c;
     if ((T & 7) == 0) {
-      const int64_t x = tile & 7, slot = tile >> 3;
-      g = slot % G;
-      c = (slot / G) * 8 + x;
+      const int64_t x = tile & 7, slot = tile >> 3, per_blk = (T >> 3) * GB;
+      const int64_t blk = slot / per_blk, rem = slot % per_blk;
+      g = blk * GB + rem % GB;
+      c = (rem / GB) * 8 + x;
     } else {
-      g = tile % G;
-      c = tile / G;
+      const int64_t per_blk = T * GB, blk = tile / per_blk, rem = tile % per_blk;
+      g = blk * GB + rem % GB;
+      c = rem / GB;
     }
     cstart = c * NCOL;
   }
