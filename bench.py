@@ -25,6 +25,24 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TOPS = 39.3216       # 256 CU x 64 lane-ops/clk x 2.4 GHz
 C_EPI_MIN = 203                # the paper's integer-epilogue ledger, low end, instructions / output
 SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
+# HBM bytes per stage launch at 1024^3 on the FP16 substrate, from the
+# FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters in
+# profiles/ob_stage_kernel_fp16_1024cubed_counters.md; valid only for the
+# kernel sources they were taken with (fingerprint below), else null.
+TRAFFIC_MEASURED = {"bytes": 34.43e9, "sources_sha256_16": "048bc1ce3d17c0c8"}
+KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_device.h",
+                  "paper_2606_23698_amd/csrc/obfft_internal.h"]
+
+
+def measured_traffic(N, substrate):
+    import hashlib
+    if N != 1024 or substrate != 2:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_MEASURED["bytes"] if h.hexdigest()[:16] == TRAFFIC_MEASURED["sources_sha256_16"] else None
 SUB_DTYPE = {0: "fp8", 1: "i8", 2: "f16"}
 
 
@@ -231,7 +249,8 @@ def main():
         "rel_l2_emulated_vs_native": diff if diff == diff else None,
         "wall_ms_per_step": round(wall, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": measured_traffic(N, info["substrate"]),
                      "kernel": "ob_stage_kernel", "avg_launch_ms": round(stage_ms, 3),
                      "algorithmic_per_launch": f"{C_EPI_MIN} integer ops x {n_out_launch} outputs"},
     }
