@@ -164,11 +164,32 @@ struct Epilogue {
     }
   }
 
-  __device__ __forceinline__ static void times_m(uint32_t zh, const CrtConsts& C, uint32_t* zm) {
+  // Lift constants held in registers for the whole epilogue (read once from
+  // the plan's device copy, never re-read inside a round).
+  struct LiftK {
+    uint32_t M[NW], negM[NW], Mhalf[NW];
+    int64_t thr;
+    uint32_t khi, zhi;
+  };
+  __device__ __forceinline__ static LiftK load_lift(const CrtConsts& C, bool exact) {
+    LiftK k;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      k.M[i] = C.M[i];
+      k.negM[i] = C.negM[i];
+      k.Mhalf[i] = C.Mhalf[i];
+    }
+    k.thr = C.thr;
+    k.khi = exact ? C.khi_x : C.khi_c;
+    k.zhi = C.zhi;
+    return k;
+  }
+
+  __device__ __forceinline__ static void times_m(uint32_t zh, const LiftK& K, uint32_t* zm) {
     uint64_t p = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
-      p = (uint64_t)zh * C.M[i] + (p >> 32);
+      p = (uint64_t)zh * K.M[i] + (p >> 32);
       zm[i] = (uint32_t)p;
     }
   }
@@ -176,24 +197,23 @@ struct Epilogue {
   // Exact two-sided lift (Sec. 5.1, Alg. 2): with W = E + M/2 + zoff M,
   // X = W - (zhat + zoff) M = E - zhat M + M/2, corrected into [0, M) from
   // either side, and R = X - M/2 in [-M/2, M/2).
-  __device__ __forceinline__ static void lift_exact(const uint32_t* w, uint32_t zh, const CrtConsts& C,
-                                                    uint32_t* R) {
+  __device__ __forceinline__ static void lift_exact(const uint32_t* w, uint32_t zh, const LiftK& K, uint32_t* R) {
     uint32_t zm[NW], X[NW], Y[NW], Z[NW], bw = 0, cy = 0;
-    times_m(zh, C, zm);
+    times_m(zh, K, zm);
 #pragma unroll
     for (int i = 0; i < NW; i++) X[i] = subc(w[i], zm[i], bw, &bw);
     bw = 0;
 #pragma unroll
-    for (int i = 0; i < NW; i++) Y[i] = subc(X[i], C.M[i], bw, &bw);
+    for (int i = 0; i < NW; i++) Y[i] = subc(X[i], K.M[i], bw, &bw);
 #pragma unroll
-    for (int i = 0; i < NW; i++) Z[i] = addc(X[i], C.M[i], cy, &cy);
+    for (int i = 0; i < NW; i++) Z[i] = addc(X[i], K.M[i], cy, &cy);
     bool xneg = (int32_t)X[NW - 1] < 0;
     bool ypos = (int32_t)Y[NW - 1] >= 0;
     bw = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
       uint32_t s = xneg ? Z[i] : (ypos ? Y[i] : X[i]);
-      R[i] = subc(s, C.Mhalf[i], bw, &bw);
+      R[i] = subc(s, K.Mhalf[i], bw, &bw);
     }
   }
 
@@ -202,17 +222,17 @@ struct Epilogue {
   // 2^(cap - 1), far under M/4, so the top 64 bits of X decide the side:
   // above thr subtract M, below -thr add M.  Equals the exact lift for every
   // value the stage kernels produce.
-  __device__ __forceinline__ static void lift_capacity(const uint32_t* w, uint32_t zh, const CrtConsts& C,
+  __device__ __forceinline__ static void lift_capacity(const uint32_t* w, uint32_t zh, const LiftK& K,
                                                        uint32_t* R) {
     uint32_t zm[NW], X[NW], bw = 0, cy = 0;
-    times_m(zh, C, zm);
+    times_m(zh, K, zm);
 #pragma unroll
     for (int i = 0; i < NW; i++) X[i] = subc(w[i], zm[i], bw, &bw);
     const int64_t top = (int64_t)(((uint64_t)X[NW - 1] << 32) | X[NW - 2]);
-    const bool hi = top > C.thr, lo = top < -C.thr;
+    const bool hi = top > K.thr, lo = top < -K.thr;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
-      uint32_t d = hi ? C.negM[i] : (lo ? C.M[i] : 0u);
+      uint32_t d = hi ? K.negM[i] : (lo ? K.M[i] : 0u);
       R[i] = addc(X[i], d, cy, &cy);
     }
   }

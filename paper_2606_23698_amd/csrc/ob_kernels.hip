@@ -557,6 +557,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   const v8h aop = *(const v8h*)(P.phaseA + lane * 8);
   const CrtConsts& C = *P.crt;
   const v16f seed = phase_a_seed(C.seedT_c, lane >> 5);
+  const typename EP::LiftK LK = EP::load_lift(C, false);
   const int64_t co = col_out[col];
   const int ex = cexp[col] - 2 * (TT::PREC - 1) + P.extra_shift;
   typename TT::T re_part = 0;
@@ -578,10 +579,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
     float xv[EP::NV], yv[EP::NV];
     phase_a<EP::NV>(aop, b1, b2, seed, xv, yv);
     uint32_t wv[TT::NW];
-    EP::deposits(xv, yv, C.khi_c, wv);
-    const uint32_t zh = EP::zhat(xv, yv, C.zhi);
+    EP::deposits(xv, yv, LK.khi, wv);
+    const uint32_t zh = EP::zhat(xv, yv, LK.zhi);
     uint32_t Rw[TT::NW];
-    EP::lift_capacity(wv, zh, C, Rw);
+    EP::lift_capacity(wv, zh, LK, Rw);
     typename TT::T y;
     if (TGT == 0)
       y = (typename TT::T)pack_f64<TT::NW>(Rw, ex);
@@ -647,10 +648,11 @@ __global__ __launch_bounds__(256) void crt_kernel(int64_t n, const uint16_t* res
   float xv[EP::NV], yv[EP::NV];
   phase_a<EP::NV>(aop, b1, b2, phase_a_seed(C.seedT_x, h), xv, yv);
   uint32_t wv[TT::NW];
-  EP::deposits(xv, yv, C.khi_x, wv);
-  const uint32_t zh = EP::zhat(xv, yv, C.zhi);
+  const typename EP::LiftK LK = EP::load_lift(C, true);
+  EP::deposits(xv, yv, LK.khi, wv);
+  const uint32_t zh = EP::zhat(xv, yv, LK.zhi);
   uint32_t Rw[TT::NW];
-  EP::lift_exact(wv, zh, C, Rw);
+  EP::lift_exact(wv, zh, LK, Rw);
   const int64_t o = base + lane;
   if (o < n) {
     const int ex = exps[o];
