@@ -246,7 +246,9 @@ __device__ __forceinline__ v16f phase_a_seed(const float (*tbl)[16], int h) {
 // space after inlining.
 extern __shared__ __align__(16) unsigned char smem[];
 
-template <int SUB, int TGT, int KMAX>
+// FULL: the contraction length equals KMAX (the common 16 x 16, 16 x 32 and
+// 32 x 32 splits), so every bound on K is known when compiling.
+template <int SUB, int TGT, int KMAX, bool FULL = false>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
@@ -258,7 +260,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   constexpr int DIG = LY::DIG;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
-  const int K = P.K;
+  const int K = FULL ? KMAX : P.K;
   int64_t* col_in = (int64_t*)(smem + 2 * DIG);
   int64_t* col_out = col_in + NCOL;
   int* cexp = (int*)(col_out + NCOL);
@@ -602,9 +604,9 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
   }
 }
 
-template <int SUB, int TGT, int KMAX>
+template <int SUB, int TGT, int KMAX, bool FULL>
 __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P) {
-  stage_tile<SUB, TGT, KMAX>(P, (int64_t)blockIdx.x);
+  stage_tile<SUB, TGT, KMAX, FULL>(P, (int64_t)blockIdx.x);
 }
 
 // Batched stage: one workgroup per tile of the members of one Bailey pass
@@ -723,28 +725,34 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
 }
 
 // ---- host-side launch helpers ----
-template <int SUB, int TGT, int KMAX>
+template <int SUB, int TGT, int KMAX, bool FULL>
 static hipError_t launch_stage_t(const StageParams& P, int64_t grid, hipStream_t st) {
   int lds = StageLds<SUB, TGT, KMAX>::bytes(P.K);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX, FULL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX>), dim3((unsigned)grid), dim3(kThreads), lds, st, P);
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL>), dim3((unsigned)grid), dim3(kThreads), lds, st, P);
   return hipGetLastError();
 }
 
+// Full-length variants for the default substrate at K = 16 and 32 (the
+// power-of-two splits); everything else takes the general kernel.
 template <int SUB, int TGT>
 static hipError_t launch_stage_k(const StageParams& P, int64_t grid, hipStream_t st) {
   int K = P.K;
-  if (K <= 4) return launch_stage_t<SUB, TGT, 4>(P, grid, st);
-  if (K <= 8) return launch_stage_t<SUB, TGT, 8>(P, grid, st);
-  if (K <= 12) return launch_stage_t<SUB, TGT, 12>(P, grid, st);
-  if (K <= 16) return launch_stage_t<SUB, TGT, 16>(P, grid, st);
-  return launch_stage_t<SUB, TGT, 32>(P, grid, st);
+  if (K <= 4) return launch_stage_t<SUB, TGT, 4, false>(P, grid, st);
+  if (K <= 8) return launch_stage_t<SUB, TGT, 8, false>(P, grid, st);
+  if (K <= 12) return launch_stage_t<SUB, TGT, 12, false>(P, grid, st);
+  if (K <= 16) {
+    if (SUB == SUB_FP16 && K == 16) return launch_stage_t<SUB, TGT, 16, SUB == SUB_FP16>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 16, false>(P, grid, st);
+  }
+  if (SUB == SUB_FP16 && K == 32) return launch_stage_t<SUB, TGT, 32, SUB == SUB_FP16>(P, grid, st);
+  return launch_stage_t<SUB, TGT, 32, false>(P, grid, st);
 }
 
 hipError_t launch_stage(int sub, int tgt, const StageParams& P, int64_t grid, hipStream_t st) {
