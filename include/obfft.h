@@ -47,7 +47,8 @@ typedef struct obfft_plan_s* obfft_plan_t;
 typedef enum {
   OBFFT_SUCCESS = 0,
   OBFFT_INVALID_VALUE = 1,        /* bad pointer, size, option or overlap */
-  OBFFT_UNSUPPORTED_SIZE = 2,     /* an extent with no admissible p x q split */
+  OBFFT_UNSUPPORTED_SIZE = 2,     /* an extent with no admissible p x q split, or
+                                     n1 n2 n3 / q >= 2^31 on some axis */
   OBFFT_CAPACITY_EXCEEDED = 3,    /* log2 M <= 1 + log2 K + 2(k+1) (Sec. 2, Eq. capacity) */
   OBFFT_NONFINITE_INPUT = 4,      /* reserved: non-finite input values */
   OBFFT_ALLOC_FAILED = 5,         /* device or host allocation failed */

@@ -13,7 +13,7 @@
 #include "plan_math.h"
 
 namespace obfft {
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, int64_t grid, hipStream_t st);
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipStream_t st);
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
@@ -175,6 +175,8 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
     plan->p[a] = pp;
     plan->q[a] = qq;
     kmax = std::max<int64_t>(kmax, std::max(pp, qq));
+    // the stage kernels index contraction columns in 31 bits
+    if ((plan->n[0] * plan->n[1] * plan->n[2]) / qq >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
   }
   // Eq. capacity: log2 M > 1 + log2 K + 2(k+1)
   if (!(plan->H.log2M > capacity_bits(kmax, plan->kbits))) return OBFFT_CAPACITY_EXCEEDED;
@@ -337,6 +339,50 @@ static bool overlaps(const void* a, const void* b, size_t bytes) {
   return x != y && x < y + bytes && y < x + bytes;
 }
 
+// n / d = mulhi(n, magic) >> shift for every n < 2^31 (magic = ceil(2^(31+l) / d),
+// l = ceil(log2 d), shift = l - 1; magic 0 encodes d = 1).
+static void div_magic(int64_t d, uint32_t* magic, uint32_t* shift) {
+  if (d <= 1) {
+    *magic = 0;
+    *shift = 0;
+    return;
+  }
+  int l = 0;
+  while (((int64_t)1 << l) < d) l++;
+  unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+  *magic = (uint32_t)((num + (unsigned __int128)d - 1) / (unsigned __int128)d);
+  *shift = (uint32_t)(l - 1);
+}
+
+// The stage kernel's grid for `tiles` tiles: a 1-, 2- or 3-D shape that spells
+// out (column tile, group) without divisions when every extent fits.
+static dim3 stage_grid(StageParams& P, int64_t tiles) {
+  const int64_t kMaxYZ = 65535;
+  if (P.stage == 1) {
+    if (tiles < ((int64_t)1 << 31)) {
+      P.grid_mode = 1;
+      return dim3((unsigned)tiles);
+    }
+  } else if (!P.g_minor) {
+    if (P.tiles_per_g < ((int64_t)1 << 31) && P.G <= kMaxYZ) {
+      P.grid_mode = 2;
+      return dim3((unsigned)P.tiles_per_g, (unsigned)P.G);
+    }
+  } else {
+    const int64_t T = P.tiles_per_g, G = P.G, GB = (G & 7) == 0 ? 8 : G;
+    if ((T & 7) == 0 && T / 8 <= kMaxYZ && G / GB <= kMaxYZ) {
+      P.grid_mode = 3;
+      return dim3((unsigned)(8 * GB), (unsigned)(T / 8), (unsigned)(G / GB));
+    }
+    if ((T & 7) != 0 && T <= kMaxYZ && G / GB <= kMaxYZ) {
+      P.grid_mode = 4;
+      return dim3((unsigned)GB, (unsigned)T, (unsigned)(G / GB));
+    }
+  }
+  P.grid_mode = 0;
+  return dim3((unsigned)tiles);
+}
+
 static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, const void* in, void* out,
                          StageParams& P, int64_t& grid) {
   memset(&P, 0, sizeof(P));
@@ -359,6 +405,8 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   P.amat_chmax = L.chmax;
   P.amat_mt = L.mt;
   P.phaseA = plan->d_phaseA;
+  div_magic(inner, &P.inner_magic, &P.inner_shift);
+  div_magic(stage == 1 ? p : q, &P.G_magic, &P.G_shift);
   P.mc = plan->d_mc;
   P.crt = plan->d_crt;
   if (stage == 1) {
@@ -389,11 +437,12 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
 static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int direction, const void* in,
                                 void* out, int extra_shift, uint16_t* dbg, hipStream_t st) {
   StageParams P;
-  int64_t grid;
-  stage_params(plan, axis, stage, direction, in, out, P, grid);
+  int64_t tiles;
+  stage_params(plan, axis, stage, direction, in, out, P, tiles);
+  const dim3 grid = stage_grid(P, tiles);
   P.extra_shift = extra_shift;
   P.dbg_res = dbg;
-  if (grid <= 0) return OBFFT_SUCCESS;
+  if (tiles <= 0) return OBFFT_SUCCESS;
   if (launch_stage(plan->substrate, plan->precision, P, grid, st) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;

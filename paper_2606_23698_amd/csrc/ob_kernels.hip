@@ -248,8 +248,67 @@ extern __shared__ __align__(16) unsigned char smem[];
 
 // FULL: the contraction length equals KMAX (the common 16 x 16, 16 x 32 and
 // 32 x 32 splits), so every bound on K is known when compiling.
+// n / d for n < 2^31 by a multiply-high with the plan's magic number.
+__device__ __forceinline__ uint32_t udiv31(uint32_t n, uint32_t magic, uint32_t shift) {
+  return magic ? (__umulhi(n, magic) >> shift) : n;
+}
+
+// (column tile, group) of linear tile index `tile` of a stage.  Stage 2 on
+// the contiguous axis (g_minor): a tile writes 16 bytes per output row at a
+// stride of q elements; the 8 tiles of one column tile with k2 = 8b .. 8b + 7
+// together fill whole 128-byte lines.  Workgroups go to the 8 XCDs round
+// robin (workgroup w on XCD w % 8), each with its own L2: XCD x takes the
+// column tiles c = 8 j + x, and for one block of 8 groups at a time runs the
+// 8 groups of a column tile back to back, so that the partial lines merge in
+// that L2 while only 8 groups' matrix planes are live in it.
+__device__ __forceinline__ void decode_tile(const StageParams& P, int64_t tile, int64_t& c, int64_t& g) {
+  if (P.stage == 1) {
+    c = tile;
+    g = 0;
+  } else if (!P.g_minor) {
+    g = tile / P.tiles_per_g;
+    c = tile % P.tiles_per_g;
+  } else {
+    const int64_t T = P.tiles_per_g, G = P.G;
+    const int64_t GB = (G & 7) == 0 ? 8 : G;
+    if ((T & 7) == 0) {
+      const int64_t x = tile & 7, slot = tile >> 3, per_blk = (T >> 3) * GB;
+      const int64_t blk = slot / per_blk, rem = slot % per_blk;
+      g = blk * GB + rem % GB;
+      c = (rem / GB) * 8 + x;
+    } else {
+      const int64_t per_blk = T * GB, blk = tile / per_blk, rem = tile % per_blk;
+      g = blk * GB + rem % GB;
+      c = rem / GB;
+    }
+  }
+}
+
+// The same order read off a 1-, 2- or 3-D grid without divisions (grid_mode):
+// the hardware's linear workgroup order is x fastest, then y, then z.
+__device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int64_t& g) {
+  const int64_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  switch (P.grid_mode) {
+    case 1: c = bx; g = 0; break;
+    case 2: c = bx; g = by; break;
+    case 3: {
+      const int64_t GB = (P.G & 7) == 0 ? 8 : P.G;
+      c = by * 8 + (bx & 7);
+      g = bz * GB + (bx >> 3);
+      break;
+    }
+    case 4: {
+      const int64_t GB = (P.G & 7) == 0 ? 8 : P.G;
+      c = by;
+      g = bz * GB + bx;
+      break;
+    }
+    default: decode_tile(P, bx, c, g);
+  }
+}
+
 template <int SUB, int TGT, int KMAX, bool FULL = false>
-__device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
+__device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, int64_t g) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
@@ -268,44 +327,20 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile addressing stays scalar
-  int64_t g = 0, cstart;
-  if (P.stage == 1) {
-    cstart = tile * NCOL;
-  } else if (!P.g_minor) {
-    g = tile / P.tiles_per_g;
-    cstart = (tile % P.tiles_per_g) * NCOL;
-  } else {
-    // Contiguous axis: a stage-2 tile writes 16 bytes per output row at a
-    // stride of q elements; the 8 tiles of one column tile with k2 = 8b ..
-    // 8b + 7 together fill whole 128-byte lines.  Workgroups go to the 8 XCDs
-    // round robin (workgroup w on XCD w % 8), each with its own L2: XCD x
-    // takes the column tiles c = 8 j + x, and for one block of 8 groups at a
-    // time runs the 8 groups of a column tile back to back, so that the
-    // partial lines merge in that L2 while only 8 groups' matrix planes are
-    // live in it.
-    const int64_t T = P.tiles_per_g, G = P.G;
-    const int64_t GB = (G & 7) == 0 ? 8 : G;
-    int64_t c;
-    if ((T & 7) == 0) {
-      const int64_t x = tile & 7, slot = tile >> 3, per_blk = (T >> 3) * GB;
-      const int64_t blk = slot / per_blk, rem = slot % per_blk;
-      g = blk * GB + rem % GB;
-      c = (rem / GB) * 8 + x;
-    } else {
-      const int64_t per_blk = T * GB, blk = tile / per_blk, rem = tile % per_blk;
-      g = blk * GB + rem % GB;
-      c = rem / GB;
-    }
-    cstart = c * NCOL;
-  }
+  const int64_t cstart = ctile * NCOL;
   if (tid < NCOL) {
-    int64_t c = cstart + tid;
+    // column c = (i, g, o) of the stage, i fastest (stage 2: g is the tile's)
+    const int64_t c = cstart + tid;
     int64_t ci = -1, co = -1;
     if (c < P.ncols) {
-      int64_t i = c % P.inner, rest = c / P.inner, o, gg;
+      const uint32_t c32 = (uint32_t)c;  // ncols < 2^31 (checked by the plan)
+      const uint32_t rest = udiv31(c32, P.inner_magic, P.inner_shift);
+      const int64_t i = (int64_t)(c32 - rest * (uint32_t)P.inner);
+      int64_t o, gg;
       if (P.stage == 1) {
-        gg = rest % P.G;
-        o = rest / P.G;
+        const uint32_t q = udiv31(rest, P.G_magic, P.G_shift);
+        gg = rest - q * (uint32_t)P.G;
+        o = q;
       } else {
         gg = g;
         o = rest;
@@ -606,7 +641,9 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t tile) {
 
 template <int SUB, int TGT, int KMAX, bool FULL>
 __global__ __launch_bounds__(kThreads) void ob_stage_kernel(const StageParams P) {
-  stage_tile<SUB, TGT, KMAX, FULL>(P, (int64_t)blockIdx.x);
+  int64_t c, g;
+  grid_tile(P, c, g);
+  stage_tile<SUB, TGT, KMAX, FULL>(P, c, g);
 }
 
 // Batched stage: one workgroup per tile of the members of one Bailey pass
@@ -620,7 +657,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
   if (t >= total) return;
   const int d = __builtin_amdgcn_readfirstlane((int)tmember[t]);  // uniform: scalar descriptor loads
   const StageParams P = descs[d];
-  stage_tile<SUB, TGT, KMAX>(P, t - first[d]);
+  int64_t c, g;
+  decode_tile(P, t - first[d], c, g);
+  stage_tile<SUB, TGT, KMAX>(P, c, g);
 }
 
 // ---- standalone CRT reconstruction (unit-level access to Phase A / B) ----
@@ -726,7 +765,7 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
 
 // ---- host-side launch helpers ----
 template <int SUB, int TGT, int KMAX, bool FULL>
-static hipError_t launch_stage_t(const StageParams& P, int64_t grid, hipStream_t st) {
+static hipError_t launch_stage_t(const StageParams& P, dim3 grid, hipStream_t st) {
   int lds = StageLds<SUB, TGT, KMAX>::bytes(P.K);
   static bool attr_set = false;
   if (!attr_set) {
@@ -735,14 +774,14 @@ static hipError_t launch_stage_t(const StageParams& P, int64_t grid, hipStream_t
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL>), dim3((unsigned)grid), dim3(kThreads), lds, st, P);
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL>), grid, dim3(kThreads), lds, st, P);
   return hipGetLastError();
 }
 
 // Full-length variants for the default substrate at K = 16 and 32 (the
 // power-of-two splits); everything else takes the general kernel.
 template <int SUB, int TGT>
-static hipError_t launch_stage_k(const StageParams& P, int64_t grid, hipStream_t st) {
+static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st) {
   int K = P.K;
   if (K <= 4) return launch_stage_t<SUB, TGT, 4, false>(P, grid, st);
   if (K <= 8) return launch_stage_t<SUB, TGT, 8, false>(P, grid, st);
@@ -755,7 +794,7 @@ static hipError_t launch_stage_k(const StageParams& P, int64_t grid, hipStream_t
   return launch_stage_t<SUB, TGT, 32, false>(P, grid, st);
 }
 
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, int64_t grid, hipStream_t st) {
+hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipStream_t st) {
   if (sub == SUB_FP16)
     return tgt == 0 ? launch_stage_k<SUB_FP16, 0>(P, grid, st)
                     : launch_stage_k<SUB_FP16, 1>(P, grid, st);

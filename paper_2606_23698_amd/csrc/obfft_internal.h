@@ -73,8 +73,13 @@ struct StageParams {
   int G;                // number of column groups (p for stage 1, q for stage 2)
   int stage;
   int tiles_per_g;      // stage 2 only
-  int g_minor;          // stage 2: tile order (0: group-major; 1: all groups of a
-                        // column tile on one XCD back to back, see stage_tile)
+  int g_minor;          // stage 2: tile order (0: group-major; 1: blocks of 8 groups
+                        // of a column tile on one XCD back to back, see stage_tile)
+  int grid_mode;        // how the stage kernel reads (column tile, group) off blockIdx:
+                        // 0 linear index, 1 stage 1 (x), 2 group-major (x, y),
+                        // 3 group-minor (8 GB, T / 8, G / GB), 4 group-minor (GB, T, G / GB)
+  uint32_t inner_magic, inner_shift, G_magic, G_shift;  // n / d = mulhi(n, magic) >> shift
+                                                        // for n < 2^31 (magic 0: d = 1)
   int extra_shift;      // added to the pack exponent
   const uint8_t* amat;  // MFMA A-operand planes of this stage / direction
   int64_t amat_g_stride;  // bytes per group g (0 for stage 1)
