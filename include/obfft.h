@@ -69,10 +69,11 @@ enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
  *   INT8 : 8-bit limbs (radix 128), v_mfma_i32_16x16x64_i8, INT32
  *          accumulation, three Karatsuba products
  *   FP16 : whole FP16 matrix residues against radix-128 data limbs (the
- *          first 5 moduli of an FP64 set, 4 of an FP32 set) or against one
+ *          first 4 moduli of an FP64 set, 3 of an FP32 set) or against one
  *          FP16 residue per index (the later moduli, each of which must
- *          satisfy 64 floor(m/2) (floor(m/2) + 2) < 2^24, else
- *          OBFFT_UNSUPPORTED_SIZE), v_mfma_f32_16x16x32_f16, exact FP32
+ *          satisfy 64 h (h + e) <= 2^24, h = floor(m/2), e = 0 for a power
+ *          of two and 2 otherwise, else OBFFT_UNSUPPORTED_SIZE),
+ *          v_mfma_f32_16x16x32_f16, exact FP32
  *          accumulation of the four real products straight into Re and Im
  *   AUTO : FP16 when the modulus set allows it (both default sets do), else
  *          INT8 */

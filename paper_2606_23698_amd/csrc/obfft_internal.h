@@ -13,11 +13,12 @@ enum Substrate { SUB_FP8 = 0, SUB_INT8 = 1, SUB_FP16 = 2, SUB_AUTO = 3 };
 
 // FP16 substrate: the first kFp16Split[precision] moduli of a set enter the
 // residue GEMM as two radix-128 limbs per index; every later modulus as one
-// FP16 slot per index, which needs 2 kMaxK floor(m/2) (floor(m/2) + 2) < 2^24
-// (the largest possible partial sum of a 32-term, two-product accumulation,
-// kept exact in FP32).  The default sets satisfy it from index 5 (r = 12:
-// 961, 841, ...) and 4 (r = 6: 961, 841).
-constexpr int kFp16Split[2] = {5, 4};
+// FP16 slot per index, which needs 2 kMaxK h (h + e) <= 2^24 with h =
+// floor(m/2), e = 0 for a power of two (its residues are exact, |r| <= h)
+// and 2 otherwise: the largest possible partial sum of a 32-term,
+// two-product accumulation, kept exact in FP32.  The default sets satisfy it
+// from index 4 (r = 12: 1024, 961, 841, ...) and 3 (r = 6: 1024, 961, 841).
+constexpr int kFp16Split[2] = {4, 3};
 
 // Everything the CRT epilogue needs: Sec. 4.2 (Phase A, byte slices of
 // u_k) and Sec. 5.1 (fractional lift, bias, M).

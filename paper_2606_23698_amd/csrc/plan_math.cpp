@@ -349,8 +349,8 @@ static void matrix_entry(const std::vector<int64_t>& roots, int64_t N, int64_t p
 }
 
 bool fp16_single_slot_ok(int m) {
-  int64_t h = m / 2;
-  return 2LL * kMaxK * h * (h + 2) < (1LL << 24);
+  const int64_t h = m / 2, e = (m & (m - 1)) == 0 ? 0 : 2;
+  return 2LL * kMaxK * h * (h + e) <= (1LL << 24);
 }
 
 void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,

@@ -75,15 +75,17 @@ def test_unsupported_and_invalid_sizes():
 
 
 def test_fp16_substrate_rejects_a_large_modulus_past_the_split():
-    """FP16 takes one slot per index for moduli 5.. of an FP64 set, which is
-    exact only when 64 floor(m/2) (floor(m/2) + 2) < 2^24 (m <= 961 of the
-    default set); 1089 at index 5 violates it."""
+    """FP16 takes one slot per index for moduli 4.. of an FP64 set, which is
+    exact only when 64 h (h + e) <= 2^24 (h = floor(m/2); e = 0 for a power
+    of two, whose residues are exact, else 2): 1024 and 961 pass, 1089 at
+    index 5 violates it."""
     from paper_2606_23698_amd import api
     from paper_2606_23698_amd._lib import ObfftError
     h = 1089 // 2
-    assert 64 * h * (h + 2) >= 2 ** 24
+    assert 64 * h * (h + 2) > 2 ** 24
     h = 961 // 2
-    assert 64 * h * (h + 2) < 2 ** 24
+    assert 64 * h * (h + 2) <= 2 ** 24
+    assert 64 * 512 * 512 == 2 ** 24          # m = 1024: exactly at the bound
     mods = [2039, 2029, 2027, 961, 1024, 1089, 841, 625, 529, 511, 491, 487]
     assert sorted(mods) == sorted(K.MODULI_FP64)
     with pytest.raises(ObfftError) as e:
