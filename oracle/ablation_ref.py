@@ -1,0 +1,101 @@
+"""Reference of the two reconstruction ablations (oracle, test infrastructure only).
+
+The paper ranks the exact Kulisch Phase B against the reconstructions it
+replaces.  Two of them are written out here, in Python integers and Python
+floats (IEEE binary64, round to nearest even), from their definitions:
+
+* recursive Garner (Sec. 4.1, paragraph on the recursive Garner count, Eq.
+  recursive-garner; App. C, per-formulation costs): the mixed-radix digits
+  of the residue tuple, each from the ones before it, then the positional
+  value, centred into [-M/2, M/2) and rounded once.  The result is the exact
+  CRT integer, so its output equals the Kulisch route's bit for bit.
+
+* slicing direct CRT with a plain FP64 sum (Sec. 4.2, Phase B paragraph on the
+  FP vector pipe; App. C, the "fp64 sum" Phase B option and Table precision):
+  the Phase-A slice sums P_s of Eq. slicing, summed as FP64 values
+  P_s * 256^s with a rounding after every addition, the modulo-M lift taken
+  with the same round(2^-48 sum_t 256^t Z_t) as the exact route but applied
+  in FP64, and one scaling by 2^exp.  This is the accuracy baseline: the
+  unweighted sum spans about 120 bits, so the cancellation against zhat M
+  loses the low bits of the result.
+
+Readings where the paper leaves the order open (recorded in the design notes):
+the FP64 sum runs over s = 0, 1, ..., S-1; M enters the FP64 lift as its
+nearest binary64 value and zhat * M is rounded before the subtraction; the
+FP32 target converts the FP64 result to binary32 at the end.
+"""
+import math
+import struct
+
+from . import constants as K
+from . import crt_ref
+
+
+def garner_digits(v, moduli):
+    """Mixed-radix digits d_k in [0, m_k) with sum_k d_k prod_{i<k} m_i = CRT(v).
+
+    Eq. recursive-garner: d_k = (v_k - sum_{j<k} d_j prod_{i<j} m_i)
+    * (prod_{i<k} m_i)^-1 mod m_k, taken for k = 0, 1, ... in order.
+    """
+    d = []
+    for k, mk in enumerate(moduli):
+        acc = v[k]
+        radix = 1  # prod_{i<j} m_i for the current j
+        for j in range(k):
+            acc -= d[j] * radix
+            radix *= moduli[j]
+        d.append(acc * pow(radix, -1, mk) % mk)
+    return d
+
+
+def garner_value(d, moduli):
+    """The positional value d_0 + m_0 (d_1 + m_1 (d_2 + ...)) in [0, M)."""
+    value = 0
+    for k in reversed(range(len(moduli))):
+        value = value * moduli[k] + d[k]
+    return value
+
+
+def garner_reconstruct(v, moduli, exp=0, target="f64"):
+    """Recursive Garner, centring into [-M/2, M/2), one correctly rounded pack."""
+    M = K.modulus_product(moduli)
+    value = garner_value(garner_digits(v, moduli), moduli)
+    R = value - M if value >= M // 2 else value
+    y = crt_ref.pack_f64(R, exp) if target == "f64" else crt_ref.pack_f32(R, exp)
+    return {"digits": garner_digits(v, moduli), "R": R, "y": y}
+
+
+def slice_fp64(v, moduli, exp=0, target="f64"):
+    """Slicing direct CRT with the plain FP64 Phase B (Sec. 4.2; App. C)."""
+    M = K.modulus_product(moduli)
+    P, Z = crt_ref.phase_a(v, moduli)
+    T = 0.0
+    for s, ps in enumerate(P):
+        T = T + float(ps) * float(1 << (8 * s))  # the product is exact; the sum rounds
+    zhat = crt_ref.zhat_from(Z)
+    lift = float(zhat) * float(M)  # float(M) is the nearest binary64 to M
+    y = math.ldexp(T - lift, exp)
+    if target == "f32":
+        y = struct.unpack("<f", struct.pack("<f", y))[0]
+    return {"P": P, "T": T, "zhat": zhat, "y": y}
+
+
+def slice_fp64_error_bound(v, moduli, exp=0):
+    """A bound on |y - R 2^exp| for slice_fp64's FP64 target (Higham, Sec. 4.2).
+
+    Recursive summation of S terms rounds S - 1 times, each by at most
+    2^-53 times the partial sum; float(M) and zhat * float(M) add at most
+    2^-53 |zhat M| each, and the final subtraction 2^-53 |y|.  With
+    |partial sums| <= sum_s P_s 256^s = E and u = 2^-53 the bound is
+    (S u E + 2 u zhat M + u (|R| + S u E + 2 u zhat M)) 2^exp, to first order
+    (a factor 1.01 covers the second-order terms).
+    """
+    M = K.modulus_product(moduli)
+    P, Z = crt_ref.phase_a(v, moduli)
+    E = sum(p << (8 * s) for s, p in enumerate(P))
+    zhat = crt_ref.zhat_from(Z)
+    R = E - zhat * M
+    u = 2.0 ** -53
+    S = len(P)
+    first = S * u * float(E) + 2 * u * float(zhat) * float(M)
+    return 1.01 * math.ldexp(first + u * (abs(float(R)) + first), exp)
