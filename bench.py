@@ -136,6 +136,43 @@ def batch_throughput(api, inputs, steps):
                         "uniform[-1,1)"}
 
 
+def crt_methods(api, inputs, steps):
+    """The reconstruction ablations on the residues of one real stage: the
+    Kulisch route, recursive Garner and the plain FP64 sum, each a standalone
+    kernel that reads the residues from HBM."""
+    import torch
+    shape = (256, 256, 256)
+    plan = api.Plan(shape)
+    x = inputs.device_uniform(shape, 4)
+    taps = torch.empty((x.numel(), 2, 12), dtype=torch.int16, device=x.device)
+    plan.stage(2, 1, x, residues=taps)
+    res = taps.view(-1, 12)
+    n = res.shape[0]
+    exps = torch.zeros(n, dtype=torch.int32, device=x.device)
+    del x
+    line = {"workload": "canonical residues of the 2^25 scalar outputs of stage 1 of the n3 axis of a "
+                        "256^3 forward FFT (uniform[-1,1) seed 4), exponent 0",
+            "n": n, "hbm_floor_ms": round(n * (24 + 4 + 8) / (HBM_PEAK_GBS * 1e9) * 1e3, 4)}
+    outs = {}
+    for m in ("kulisch", "garner", "slice_fp64"):
+        o = torch.empty(n, dtype=torch.float64, device=res.device)
+        ms, _ = time_steps(lambda m=m, o=o: api.crt_reconstruct_method(res, exps, m, out=o), steps, 2)
+        outs[m] = o
+        line[m] = {"ms": round(ms, 4), "ns_per_output": round(ms * 1e6 / n, 5)}
+    exact = outs["kulisch"]
+    line["garner"]["bit_identical_to_kulisch"] = bool(torch.equal(outs["garner"].view(torch.int64),
+                                                                  exact.view(torch.int64)))
+    d = outs["slice_fp64"] - exact
+    nz = exact != 0
+    line["slice_fp64"]["rel_l2_vs_exact"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(exact))
+    line["slice_fp64"]["max_rel_vs_exact"] = float((d[nz].abs() / exact[nz].abs()).max())
+    print("[bench] crt methods (ms): " + " ".join(f"{m} {line[m]['ms']:.3f}" for m in outs) +
+          f"; fp64-sum rel err {line['slice_fp64']['rel_l2_vs_exact']:.2e}", file=sys.stderr, flush=True)
+    del outs, exact, d, res, taps, plan
+    torch.cuda.empty_cache()
+    return line
+
+
 def cpu_baseline(N, pq, target_s=12.0):
     """The exact-pipeline oracle on a bounded sample of axis passes, scaled to one transform.
 
@@ -177,6 +214,7 @@ def main():
     ap.add_argument("--no-native", action="store_true", help="skip the native FP64 comparator")
     ap.add_argument("--no-sweep", action="store_true", help="skip the FP8 / INT8 / FP32-target sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-transform batched measurement")
+    ap.add_argument("--no-crt", action="store_true", help="skip the reconstruction-method comparison")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the input (a known-size reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -260,6 +298,8 @@ def main():
         del x, y
         torch.cuda.empty_cache()
         line["batch64"] = batch_throughput(api, inputs, max(2, min(args.steps, 5)))
+    if not args.no_crt:
+        line["crt_methods"] = crt_methods(api, inputs, max(5, min(args.steps, 10)))
     if not args.no_cpu:
         try:
             line["cpu_baseline"] = cpu_baseline(N, (info["p"][2], info["q"][2]))

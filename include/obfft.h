@@ -162,9 +162,35 @@ obfft_status_t obfft_stage(obfft_plan_t plan, int axis, int stage, int direction
  *             larger values are a caller error (results undefined, no fault).
  *   exps:     device int32 [n]; output i is RNE(R_i * 2^exps[i]).
  *   out:      device double [n] (FP64) or float [n] (FP32).
- *   taps:     device uint32 [n][layout.stride] or NULL; see obfft_taps_layout. */
+ *   taps:     device uint32 [n][layout.stride] or NULL; see obfft_taps_layout.
+ * n >= 2^31 returns OBFFT_UNSUPPORTED_SIZE. */
 obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const void* residues,
                                      const void* exps, void* out, void* taps, void* stream);
+
+/* Reconstruction methods for obfft_crt_reconstruct_method: the Kulisch
+ * route above and two of the reconstructions the paper ranks it against. */
+enum {
+  OBFFT_CRT_KULISCH = 0,    /* Phase A on FP16 MFMA + Kulisch Phase B (as obfft_crt_reconstruct) */
+  OBFFT_CRT_GARNER = 1,     /* recursive Garner (Sec. 4.1, Eq. recursive-garner; App. C): mixed-
+                               radix digits in 32-bit integer arithmetic, the positional value in
+                               multiword integers, one correctly rounded pack.  Exact: the same
+                               output bits as OBFFT_CRT_KULISCH for every residue tuple. */
+  OBFFT_CRT_SLICE_FP64 = 2  /* slicing direct CRT with a plain FP64 Phase B (Sec. 4.2; App. C,
+                               Table precision): the exact Phase-A slice sums P_s, then
+                               T = sum_s P_s 256^s in FP64 (s ascending, one rounding per
+                               addition), y = T - fl(zhat * fl(M)) with zhat the lift of Sec. 5.1,
+                               scaled by 2^exps[i]; FP32 target: y rounded to binary32.  The
+                               accuracy baseline: not exact, it keeps about the top 53 of the
+                               sum's ~120 bits. */
+};
+
+/* The standalone reconstruction by one of the methods above, for timing and
+ * accuracy comparisons on the same residues.  Arguments as for
+ * obfft_crt_reconstruct (no taps).  An unknown method or precision returns
+ * OBFFT_INVALID_VALUE; n >= 2^31 returns OBFFT_UNSUPPORTED_SIZE; residues at
+ * or above their modulus give undefined values (no fault). */
+obfft_status_t obfft_crt_reconstruct_method(int precision, int method, int64_t n, const void* residues,
+                                            const void* exps, void* out, void* stream);
 
 /* Word offsets inside one output's taps record of obfft_crt_reconstruct:
  *   P    [P, P+S)        Phase-A slice sums P_s (Eq. slicing)

@@ -66,6 +66,7 @@ def lib():
         "fft3d_z2z_native_inverse": (i32, [vp, vp, vp, vp]),
         "obfft_stage": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
         "obfft_crt_reconstruct": (i32, [i32, i64, vp, vp, vp, vp, vp]),
+        "obfft_crt_reconstruct_method": (i32, [i32, i32, i64, vp, vp, vp, vp]),
         "obfft_taps_layout": (None, [P(TapsLayout)]),
         "obfft_mfma_probe": (i32, [i32, vp, vp, vp, vp]),
         "obfft_quantised_roots": (i32, [i64, i32, P(i64)]),
@@ -100,6 +101,6 @@ EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", 
             "obfft_workspace_size", "obfft_set_workspace", "obfft_plan_roots", "fft3d_z2z_forward",
             "fft3d_z2z_inverse", "fft3d_z2z_adjoint", "fft3d_c2c_forward", "fft3d_c2c_inverse",
             "fft3d_z2z_native_forward", "fft3d_z2z_native_inverse", "obfft_stage",
-            "obfft_crt_reconstruct", "obfft_taps_layout", "obfft_mfma_probe",
+            "obfft_crt_reconstruct", "obfft_crt_reconstruct_method", "obfft_taps_layout", "obfft_mfma_probe",
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
             "obfft_batch_forward", "obfft_batch_set_graph", "obfft_status_string", "obfft_last_error"]

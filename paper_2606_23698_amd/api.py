@@ -142,12 +142,15 @@ class Plan:
         """One Bailey stage of one axis; residues (int16 [numel, 2, r]) receives the tap."""
         x = _materialise(x)
         _check_dev(x, self.cdtype, name="input")
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"input shape {tuple(x.shape)} != plan shape {self.shape}")
         if out is None:
             out = torch.empty_like(x)
         _check_dev(out, self.cdtype, x.numel(), name="output")
         rp = ctypes.c_void_p(0)
         if residues is not None:
-            _check_dev(residues, torch.int16, name="residues")
+            r = 12 if self.cdtype == torch.complex128 else 6
+            _check_dev(residues, torch.int16, x.numel() * 2 * r, name="residues")
             rp = _ptr(residues)
         L.check(L.lib().obfft_stage(self._h, axis, stage, direction, _ptr(x), _ptr(out), rp,
                                     _stream(stream)), "obfft_stage")
@@ -232,10 +235,17 @@ def native_ifft3(x, out=None):
     return get_plan(x.shape, "fp64", "auto", x.device.index).native_inverse(x, out)
 
 
+def _check_residues(residues, precision):
+    r = 12 if precision == "fp64" else 6
+    _check_dev(residues, torch.int16, name="residues")
+    if residues.dim() != 2 or residues.shape[1] != r:
+        raise ValueError(f"residues must have shape [n, {r}] for {precision}, got {tuple(residues.shape)}")
+
+
 def crt_reconstruct(residues, exps, precision="fp64", taps=False, stream=None):
     """Phase A + Kulisch Phase B of n scalars: residues int16 [n, r] (canonical), exps int32 [n]."""
+    _check_residues(residues, precision)
     n = residues.shape[0]
-    _check_dev(residues, torch.int16, name="residues")
     _check_dev(exps, torch.int32, n, name="exps")
     out = torch.empty(n, dtype=torch.float64 if precision == "fp64" else torch.float32,
                       device=residues.device)
@@ -248,6 +258,25 @@ def crt_reconstruct(residues, exps, precision="fp64", taps=False, stream=None):
     L.check(L.lib().obfft_crt_reconstruct(PRECISIONS[precision], n, _ptr(residues), _ptr(exps),
                                           _ptr(out), tptr, _stream(stream)), "obfft_crt_reconstruct")
     return out, tp
+
+
+CRT_METHODS = {"kulisch": 0, "garner": 1, "slice_fp64": 2}
+
+
+def crt_reconstruct_method(residues, exps, method, precision="fp64", out=None, stream=None):
+    """One of the reconstruction methods (kulisch, garner, slice_fp64) of n scalars:
+    residues int16 [n, r] (canonical), exps int32 [n]."""
+    _check_residues(residues, precision)
+    n = residues.shape[0]
+    _check_dev(exps, torch.int32, n, name="exps")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty(n, dtype=dt, device=residues.device)
+    _check_dev(out, dt, n, name="out")
+    L.check(L.lib().obfft_crt_reconstruct_method(PRECISIONS[precision], CRT_METHODS[method], n,
+                                                 _ptr(residues), _ptr(exps), _ptr(out), _stream(stream)),
+            "obfft_crt_reconstruct_method")
+    return out
 
 
 def taps_layout():

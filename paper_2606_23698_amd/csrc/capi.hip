@@ -16,6 +16,8 @@ namespace obfft {
 hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipStream_t st);
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
+hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
+                              void* out, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
@@ -175,8 +177,13 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
     plan->p[a] = pp;
     plan->q[a] = qq;
     kmax = std::max<int64_t>(kmax, std::max(pp, qq));
-    // the stage kernels index contraction columns in 31 bits
-    if ((plan->n[0] * plan->n[1] * plan->n[2]) / qq >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
+    // the stage kernels index contraction columns in 31 bits, and a launch
+    // holds fewer than kMaxTiles workgroups
+    const int64_t n_all = plan->n[0] * plan->n[1] * plan->n[2];
+    if (n_all / qq >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
+    const int64_t c1 = stage_cols_per_wg(qq), c2 = stage_cols_per_wg(pp);
+    if ((n_all / qq + c1 - 1) / c1 >= kMaxTiles || qq * ((n_all / N + c2 - 1) / c2) >= kMaxTiles)
+      return OBFFT_UNSUPPORTED_SIZE;
   }
   // Eq. capacity: log2 M > 1 + log2 K + 2(k+1)
   if (!(plan->H.log2M > capacity_bits(kmax, plan->kbits))) return OBFFT_CAPACITY_EXCEEDED;
@@ -359,12 +366,12 @@ static void div_magic(int64_t d, uint32_t* magic, uint32_t* shift) {
 static dim3 stage_grid(StageParams& P, int64_t tiles) {
   const int64_t kMaxYZ = 65535;
   if (P.stage == 1) {
-    if (tiles < ((int64_t)1 << 31)) {
+    if (tiles < kMaxTiles) {
       P.grid_mode = 1;
       return dim3((unsigned)tiles);
     }
   } else if (!P.g_minor) {
-    if (P.tiles_per_g < ((int64_t)1 << 31) && P.G <= kMaxYZ) {
+    if (P.tiles_per_g < kMaxTiles && P.G <= kMaxYZ) {
       P.grid_mode = 2;
       return dim3((unsigned)P.tiles_per_g, (unsigned)P.G);
     }
@@ -553,37 +560,63 @@ struct CrtCache {
 static std::mutex g_crt_mu;
 static std::map<std::pair<int, int>, CrtCache> g_crt;
 
+// Constants of the standalone reconstruction for one precision on the
+// current device, built on first use.
+static obfft_status_t crt_cache(int precision, CrtCache** out) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_crt_mu);
+  CrtCache* cc = &g_crt[std::make_pair(dev, precision)];
+  if (!cc->ready) {
+    ModSet H;
+    std::string err;
+    if (!build_modset(precision ? kModFP32 : kModFP64, precision ? 6 : 12, H, err)) return OBFFT_INVALID_VALUE;
+    build_crt_consts(H, cc->C);
+    std::vector<uint16_t> pa;
+    int npairs = 0;
+    build_phaseA_operand(H, pa, &npairs);
+    if (!cc->d_phaseA && hipMalloc(&cc->d_phaseA, pa.size() * 2) != hipSuccess) return OBFFT_ALLOC_FAILED;
+    if (hipMemcpy(cc->d_phaseA, pa.data(), pa.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+      return OBFFT_HIP_ERROR;
+    if (!cc->d_C && hipMalloc(&cc->d_C, sizeof(CrtConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
+    if (hipMemcpy(cc->d_C, &cc->C, sizeof(CrtConsts), hipMemcpyHostToDevice) != hipSuccess)
+      return OBFFT_HIP_ERROR;
+    cc->ready = true;
+  }
+  *out = cc;
+  return OBFFT_SUCCESS;
+}
+
 extern "C" obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const void* residues, const void* exps,
                                                 void* out, void* taps, void* stream) {
   if ((precision != 0 && precision != 1) || n < 0 || (n > 0 && (!residues || !exps || !out)))
     return OBFFT_INVALID_VALUE;
+  if (n >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
   if (n == 0) return OBFFT_SUCCESS;
   if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
-  int dev = 0;
-  hipGetDevice(&dev);
-  CrtCache* cc;
-  {
-    std::lock_guard<std::mutex> lk(g_crt_mu);
-    cc = &g_crt[std::make_pair(dev, precision)];
-    if (!cc->ready) {
-      ModSet H;
-      std::string err;
-      if (!build_modset(precision ? kModFP32 : kModFP64, precision ? 6 : 12, H, err)) return OBFFT_INVALID_VALUE;
-      build_crt_consts(H, cc->C);
-      std::vector<uint16_t> pa;
-      int npairs = 0;
-      build_phaseA_operand(H, pa, &npairs);
-      if (hipMalloc(&cc->d_phaseA, pa.size() * 2) != hipSuccess) return OBFFT_ALLOC_FAILED;
-      if (hipMemcpy(cc->d_phaseA, pa.data(), pa.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
-        return OBFFT_HIP_ERROR;
-      if (hipMalloc(&cc->d_C, sizeof(CrtConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
-      if (hipMemcpy(cc->d_C, &cc->C, sizeof(CrtConsts), hipMemcpyHostToDevice) != hipSuccess)
-        return OBFFT_HIP_ERROR;
-      cc->ready = true;
-    }
-  }
+  CrtCache* cc = nullptr;
+  obfft_status_t st = crt_cache(precision, &cc);
+  if (st != OBFFT_SUCCESS) return st;
   if (launch_crt(precision, n, (const uint16_t*)residues, (const int*)exps, out, (uint32_t*)taps, cc->d_phaseA,
                  cc->d_C, (hipStream_t)stream) != hipSuccess)
+    return OBFFT_HIP_ERROR;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_crt_reconstruct_method(int precision, int method, int64_t n, const void* residues,
+                                                       const void* exps, void* out, void* stream) {
+  if ((precision != 0 && precision != 1) || method < OBFFT_CRT_KULISCH || method > OBFFT_CRT_SLICE_FP64 ||
+      n < 0 || (n > 0 && (!residues || !exps || !out)))
+    return OBFFT_INVALID_VALUE;
+  if (n >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
+  if (method == OBFFT_CRT_KULISCH) return obfft_crt_reconstruct(precision, n, residues, exps, out, nullptr, stream);
+  if (n == 0) return OBFFT_SUCCESS;
+  if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
+  CrtCache* cc = nullptr;
+  obfft_status_t st = crt_cache(precision, &cc);
+  if (st != OBFFT_SUCCESS) return st;
+  if (launch_crt_ablation(precision, method, n, (const uint16_t*)residues, (const int*)exps, out, cc->d_phaseA,
+                          cc->d_C, (hipStream_t)stream) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;
 }
@@ -688,6 +721,10 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
         acc += tiles[pass * count + i];
       }
       bp->batch_total[pass][c] = acc;
+      if (acc >= kMaxTiles) {
+        obfft_plan_destroy(bp);
+        return OBFFT_UNSUPPORTED_SIZE;
+      }
     }
   }
   int64_t ttot = 0;

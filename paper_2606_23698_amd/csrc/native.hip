@@ -10,6 +10,7 @@
 // path the Ozaki-Bailey kernel is measured against.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -376,15 +377,16 @@ static hipError_t launch_native_axis(const double2* in, double2* out, const NatA
 }
 
 __global__ void scale_kernel(void* data, int64_t n, double f, int tgt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (tgt == 0) ((double*)data)[i] *= f;
-  else ((float*)data)[i] = (float)((double)((float*)data)[i] * f);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (tgt == 0) ((double*)data)[i] *= f;
+    else ((float*)data)[i] = (float)((double)((float*)data)[i] * f);
+  }
 }
 
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st) {
-  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n_scalars + 255) / 256)), dim3(256), 0, st, data, n_scalars,
-                     factor, tgt);
+  const int64_t blocks = std::min<int64_t>((n_scalars + 255) / 256, (int64_t)1 << 20);
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, data, n_scalars, factor, tgt);
   return hipGetLastError();
 }
 

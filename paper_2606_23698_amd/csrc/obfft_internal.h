@@ -7,6 +7,8 @@ namespace obfft {
 constexpr int kMaxModuli = 16;
 constexpr int kMaxK = 32;          // longest contraction (p or q) of the fused stage kernel
 constexpr int kThreads = 256;      // 4 waves of 64
+// A launch's x extent in work-items is a 32-bit field: tiles per x row < 2^32 / kThreads.
+constexpr int64_t kMaxTiles = ((int64_t)1 << 32) / kThreads;
 constexpr int kTapStride = 40;     // uint32 words per output in the CRT debug taps
 
 enum Substrate { SUB_FP8 = 0, SUB_INT8 = 1, SUB_FP16 = 2, SUB_AUTO = 3 };
@@ -50,6 +52,13 @@ struct CrtConsts {
   float seedT_x[2][16];  // seed_x[2 v + h] at [h][v]: one lane half's registers
   float seedT_c[2][16];  // same for seed_c
   uint32_t Bp5[5];       // sum_s bits(seed_x[s]) 256^s mod 2^160 (debug taps only)
+  // Reconstruction ablations.  Recursive Garner (Eq. recursive-garner): m_k,
+  // the Barrett multiplier ceil(2^32 / m_k), (prod_{i<k} m_i)^-1 mod m_k and,
+  // at [k][j] for j < k, m_k - (prod_{i<j} m_i mod m_k).  Plain FP64 sum:
+  // M rounded to binary64.
+  uint32_t gm[16], gmagic[16], ginv[16];
+  uint32_t gneg[16][16];
+  double Mf;
 };
 
 // Per-modulus constants of the residue arithmetic.

@@ -189,6 +189,32 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
       C.seedT_x[h][v] = C.seed_x[2 * v + h];
       C.seedT_c[h][v] = C.seed_c[2 * v + h];
     }
+  // recursive Garner: mixed-radix weights prod_{i<j} m_i reduced mod m_k
+  for (int k = 0; k < H.r; k++) {
+    const uint64_t mk = (uint64_t)H.m[k];
+    C.gm[k] = (uint32_t)mk;
+    C.gmagic[k] = (uint32_t)((((uint64_t)1 << 32) + mk - 1) / mk);
+    uint64_t radix = 1 % mk;  // prod_{i<j} m_i mod m_k
+    for (int j = 0; j < k; j++) {
+      C.gneg[k][j] = (uint32_t)(mk - radix);
+      radix = radix * (uint64_t)H.m[j] % mk;
+    }
+    C.ginv[k] = (uint32_t)modinv((int64_t)radix, (int64_t)mk);
+  }
+  // nearest binary64 to M: the top 53 significant bits, ties to even
+  {
+    const int nb = bitlen(H.M);
+    u128 q = H.M;
+    int e = 0;
+    if (nb > 53) {
+      const int sh = nb - 53;
+      q = H.M >> sh;
+      const u128 rem = H.M & ((((u128)1) << sh) - 1), half = ((u128)1) << (sh - 1);
+      if (rem > half || (rem == half && (q & 1))) q += 1;
+      e = sh;
+    }
+    C.Mf = std::ldexp((double)(uint64_t)q, e);
+  }
 }
 
 // ---- double-double trigonometry ----
