@@ -1,4 +1,4 @@
-"""Reference of the two reconstruction ablations (oracle, test infrastructure only).
+"""Reference of the reconstruction ablations (oracle, test infrastructure only).
 
 The paper ranks the exact Kulisch Phase B against the reconstructions it
 replaces.  Two of them are written out here, in Python integers and Python
@@ -18,6 +18,17 @@ floats (IEEE binary64, round to nearest even), from their definitions:
   in FP64, and one scaling by 2^exp.  This is the accuracy baseline: the
   unweighted sum spans about 120 bits, so the cancellation against zhat M
   loses the low bits of the result.
+
+A third route keeps the Kulisch Phase B but moves Phase A to the INT8
+matrix cores (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq. h1-group): each
+canonical residue is split v = v0 + 256 v1 with v0 in [-128, 128) and v1 in
+[0, 8], both signed bytes, and the high limb multiplies the next lower slice
+(the shifted-column identity), so the columns are P'_s = sum_k (v0_k u_{k,s}
++ v1_k u_{k,s-1}) and likewise Z'_t over the lift weights.  The matrix cores
+here multiply signed bytes only, so the slices of u_k and w_k are taken as
+balanced base-256 digits in [-128, 128) (one more digit than the unsigned
+bytes); sum_s 256^s P'_s is still sum_k v_k u_k, so the result is the
+Kulisch route's bit for bit.
 
 Readings where the paper leaves the order open (recorded in the design notes):
 the FP64 sum runs over s = 0, 1, ..., S-1; M enters the FP64 lift as its
@@ -99,3 +110,47 @@ def slice_fp64_error_bound(v, moduli, exp=0):
     S = len(P)
     first = S * u * float(E) + 2 * u * float(zhat) * float(M)
     return 1.01 * math.ldexp(first + u * (abs(float(R)) + first), exp)
+
+
+def balanced_bytes(value, count):
+    """Digits d_s in [-128, 128) with sum_s d_s 256^s = value, s < count."""
+    d = []
+    for _ in range(count):
+        r = value & 0xFF
+        if r >= 128:
+            r -= 256
+        d.append(r)
+        value = (value - r) >> 8
+    assert value == 0, "too few digits"
+    return d
+
+
+def int8_limbs(v):
+    """The two-limb split of a canonical residue: v = v0 + 256 v1 (Sec. 8.3)."""
+    v0 = (v + 128) % 256 - 128
+    return v0, (v - v0) // 256
+
+
+def int8_phase_a(v, moduli):
+    """Shifted-column Phase A on signed bytes: P'_s, s <= S + 1, and Z'_t, t <= T + 1."""
+    U = [balanced_bytes(u, K.n_slices(moduli) + 1) for u in K.idempotents(moduli)]
+    W = [balanced_bytes(w, K.n_frac_slices(moduli) + 1) for w in K.lift_weights(moduli)]
+    limbs = [int8_limbs(x) for x in v]
+
+    def columns(D):
+        n = len(D[0]) + 1
+        return [sum(l0 * (D[k][s] if s < n - 1 else 0) + l1 * (D[k][s - 1] if s >= 1 else 0)
+                    for k, (l0, l1) in enumerate(limbs)) for s in range(n)]
+    return columns(U), columns(W)
+
+
+def int8_reconstruct(v, moduli, exp=0, target="f64"):
+    """Phase A on INT8 (two limbs, shifted columns), then the Kulisch Phase B of Sec. 5.1."""
+    M = K.modulus_product(moduli)
+    P, Z = int8_phase_a(v, moduli)
+    E = sum(p << (8 * s) for s, p in enumerate(P))
+    zacc = sum(z << (8 * t) for t, z in enumerate(Z))
+    zhat = (zacc + (1 << (K.FRAC_BITS - 1))) >> K.FRAC_BITS
+    R = crt_ref.two_sided_lift(E, zhat, M)
+    y = crt_ref.pack_f64(R, exp) if target == "f64" else crt_ref.pack_f32(R, exp)
+    return {"P": P, "Z": Z, "E": E, "zhat": zhat, "R": R, "y": y}

@@ -1,4 +1,4 @@
-"""Pins of the reconstruction-ablation oracle (recursive Garner, plain FP64 sum); no GPU.
+"""Pins of the reconstruction-ablation oracle (Garner, plain FP64 sum, INT8 Phase A); no GPU.
 
 Garner is pinned to the mixed-radix representation obtained by repeated
 division (a different computation from the paper's recursion), to textbook
@@ -6,6 +6,10 @@ examples worked by hand, and to the Kulisch route of oracle.crt_ref (CRT by
 idempotents).  The FP64-sum baseline is pinned to a forward error bound of
 recursive summation (any dropped slice, wrong weight or wrong sign of the
 lift lands far outside it) and to the exact special case of a zero tuple.
+The INT8 Phase A is pinned to the defining identities of its columns
+(sum_s 256^s P'_s = sum_k v_k u_k with the plain u_k, not the byte slices of
+the FP16 route), to their INT32 bound, to hand-worked digit examples and to
+the FP16 route's final values.
 """
 from fractions import Fraction
 
@@ -97,3 +101,48 @@ def test_slice_fp64_loses_low_bits_at_the_capacity_scale():
         assert A.garner_reconstruct(v, moduli)["y"] == crt_ref.pack_f64(C, 0)
     med = float(np.median(rel))
     assert 2.0 ** -45 < med < 2.0 ** -30
+
+
+# ---- Phase A on signed bytes: two limbs, shifted columns (Sec. 8.3) ----
+
+def test_balanced_bytes_and_limbs_hand_examples():
+    assert A.balanced_bytes(200, 2) == [-56, 1]                 # 200 = -56 + 256
+    assert A.balanced_bytes(0x7F80, 3) == [-128, -128, 1]       # -128 - 128*256 + 65536
+    assert A.int8_limbs(2038) == (-10, 8)                       # 2038 = -10 + 256 * 8
+    assert A.int8_limbs(127) == (127, 0)
+    assert A.int8_limbs(128) == (-128, 1)
+    assert A.int8_limbs(0) == (0, 0)
+
+
+@pytest.mark.parametrize("moduli", [K.MODULI_FP64, K.MODULI_FP32], ids=["fp64", "fp32"])
+def test_int8_columns_sum_to_the_crt_inner_products(moduli):
+    """sum_s 256^s P'_s = sum_k v_k u_k and sum_t 256^t Z'_t = sum_k v_k w_k, with
+    every column inside r * 128 * (128 + 8) (signed bytes, INT32 accumulation)."""
+    rng = np.random.default_rng(15)
+    U, W = K.idempotents(moduli), K.lift_weights(moduli)
+    bound = len(moduli) * 128 * (128 + 8)
+    tuples = [[m - 1 for m in moduli], [0] * len(moduli), [min(127, m - 1) for m in moduli],
+              [min(128, m - 1) for m in moduli]]
+    tuples += [[int(rng.integers(0, m)) for m in moduli] for _ in range(300)]
+    for v in tuples:
+        P, Z = A.int8_phase_a(v, moduli)
+        assert len(P) == K.n_slices(moduli) + 2 and len(Z) == K.n_frac_slices(moduli) + 2
+        assert sum(p << (8 * s) for s, p in enumerate(P)) == sum(a * b for a, b in zip(v, U))
+        assert sum(z << (8 * t) for t, z in enumerate(Z)) == sum(a * b for a, b in zip(v, W))
+        assert max(abs(x) for x in P + Z) <= bound < 2 ** 31
+
+
+@pytest.mark.parametrize("moduli,target", [(K.MODULI_FP64, "f64"), (K.MODULI_FP32, "f32")], ids=["fp64", "fp32"])
+def test_int8_route_equals_fp16_route(moduli, target):
+    M = K.modulus_product(moduli)
+    h = M // 2
+    rng = np.random.default_rng(16)
+    vals = [0, 1, -1, h - 1, -h, -h + 1, (1 << 53) + 1]
+    vals += [int.from_bytes(rng.bytes(16), "little") % M - h for _ in range(200)]
+    for C in vals:
+        v = [C % m for m in moduli]
+        exp = int(rng.integers(-200, 10))
+        a = A.int8_reconstruct(v, moduli, exp, target)
+        b = crt_ref.reconstruct(v, moduli, exp, target)
+        assert a["R"] == C == b["R"] and a["zhat"] == b["zhat"]
+        assert np.float64(a["y"]).tobytes() == np.float64(b["y"]).tobytes()
