@@ -29,7 +29,7 @@ SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters in
 # profiles/ob_stage_kernel_fp16_1024cubed_counters.md; valid only for the
 # kernel sources they were taken with (fingerprint below), else null.
-TRAFFIC_MEASURED = {"bytes": 34.48e9, "sources_sha256_16": "81caee53732e7b00"}
+TRAFFIC_MEASURED = {"bytes": 34.49e9, "sources_sha256_16": "ccc122d91138ad22"}
 KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_device.h",
                   "paper_2606_23698_amd/csrc/ob_recon.h", "paper_2606_23698_amd/csrc/obfft_internal.h"]
 
@@ -138,8 +138,9 @@ def batch_throughput(api, inputs, steps):
 
 def crt_methods(api, inputs, steps):
     """The reconstruction ablations on the residues of one real stage: the
-    Kulisch route, recursive Garner and the plain FP64 sum, each a standalone
-    kernel that reads the residues from HBM."""
+    Kulisch route with Phase A on FP16 and on INT8 MFMA, recursive Garner and
+    the plain FP64 sum, each a standalone kernel that reads the residues from
+    HBM."""
     import torch
     shape = (256, 256, 256)
     plan = api.Plan(shape)
@@ -154,14 +155,14 @@ def crt_methods(api, inputs, steps):
                         "256^3 forward FFT (uniform[-1,1) seed 4), exponent 0",
             "n": n, "hbm_floor_ms": round(n * (24 + 4 + 8) / (HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     outs = {}
-    for m in ("kulisch", "garner", "slice_fp64"):
+    for m in ("kulisch", "kulisch_int8", "garner", "slice_fp64"):
         o = torch.empty(n, dtype=torch.float64, device=res.device)
         ms, _ = time_steps(lambda m=m, o=o: api.crt_reconstruct_method(res, exps, m, out=o), steps, 2)
         outs[m] = o
         line[m] = {"ms": round(ms, 4), "ns_per_output": round(ms * 1e6 / n, 5)}
     exact = outs["kulisch"]
-    line["garner"]["bit_identical_to_kulisch"] = bool(torch.equal(outs["garner"].view(torch.int64),
-                                                                  exact.view(torch.int64)))
+    for m in ("kulisch_int8", "garner"):
+        line[m]["bit_identical_to_kulisch"] = bool(torch.equal(outs[m].view(torch.int64), exact.view(torch.int64)))
     d = outs["slice_fp64"] - exact
     nz = exact != 0
     line["slice_fp64"]["rel_l2_vs_exact"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(exact))

@@ -175,13 +175,18 @@ enum {
                                radix digits in 32-bit integer arithmetic, the positional value in
                                multiword integers, one correctly rounded pack.  Exact: the same
                                output bits as OBFFT_CRT_KULISCH for every residue tuple. */
-  OBFFT_CRT_SLICE_FP64 = 2  /* slicing direct CRT with a plain FP64 Phase B (Sec. 4.2; App. C,
+  OBFFT_CRT_SLICE_FP64 = 2, /* slicing direct CRT with a plain FP64 Phase B (Sec. 4.2; App. C,
                                Table precision): the exact Phase-A slice sums P_s, then
                                T = sum_s P_s 256^s in FP64 (s ascending, one rounding per
                                addition), y = T - fl(zhat * fl(M)) with zhat the lift of Sec. 5.1,
                                scaled by 2^exps[i]; FP32 target: y rounded to binary32.  The
                                accuracy baseline: not exact, it keeps about the top 53 of the
                                sum's ~120 bits. */
+  OBFFT_CRT_KULISCH_INT8 = 3 /* the Kulisch route with Phase A on INT8 MFMA (Sec. 8.2, the B200
+                               cross-check; Sec. 8.3, Eq. h1-group): residues split into two
+                               signed-byte limbs v = v0 + 256 v1, the high limb against the next
+                               lower slice, slices of u_k and w_k as balanced base-256 digits,
+                               exact INT32 accumulation.  Same output bits as OBFFT_CRT_KULISCH. */
 };
 
 /* The standalone reconstruction by one of the methods above, for timing and
@@ -209,7 +214,8 @@ void obfft_taps_layout(obfft_taps_layout_t* layout);
  * (64 x 16 bytes, d: 64 x 4 int32); 2: FP16 32x32x16 (64 x 8 half, d: 64 x
  * 16 float); 3: permlane32 swap (a, b: 64 uint32, d: 2 x 64 uint32); 4: E4M3
  * conversion of 64 floats in a (b unused) into 64 bytes of d; 5: FP16
- * 16x16x32 (64 x 8 half, d: 64 x 4 float). */
+ * 16x16x32 (64 x 8 half, d: 64 x 4 float); 6: INT8 32x32x32 (64 x 16 bytes,
+ * d: 64 x 16 int32). */
 obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream);
 
 /* Host-only introspection (no device needed). */

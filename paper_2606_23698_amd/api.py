@@ -260,11 +260,11 @@ def crt_reconstruct(residues, exps, precision="fp64", taps=False, stream=None):
     return out, tp
 
 
-CRT_METHODS = {"kulisch": 0, "garner": 1, "slice_fp64": 2}
+CRT_METHODS = {"kulisch": 0, "garner": 1, "slice_fp64": 2, "kulisch_int8": 3}
 
 
 def crt_reconstruct_method(residues, exps, method, precision="fp64", out=None, stream=None):
-    """One of the reconstruction methods (kulisch, garner, slice_fp64) of n scalars:
+    """One of the reconstruction methods (kulisch, garner, slice_fp64, kulisch_int8) of n scalars:
     residues int16 [n, r] (canonical), exps int32 [n]."""
     _check_residues(residues, precision)
     n = residues.shape[0]
@@ -285,7 +285,19 @@ def taps_layout():
     return {n: getattr(t, n) for n, _ in L.TapsLayout._fields_}
 
 
+# bytes of (a and b, d) of each probe kind (one register set per lane, 64 lanes)
+_PROBE_BYTES = {0: (512, 1024), 1: (1024, 1024), 2: (1024, 4096), 3: (256, 512), 4: (256, 64),
+                5: (1024, 1024), 6: (1024, 4096)}
+
+
 def mfma_probe(kind, a, b, d, stream=None):
+    need_ab, need_d = _PROBE_BYTES[kind]
+    for name, t, need in (("a", a, need_ab), ("b", b, need_ab if kind != 4 else 0), ("d", d, need_d)):
+        if t is None and need == 0:
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or \
+                t.numel() * t.element_size() < need:
+            raise ValueError(f"probe {kind}: {name} must be a contiguous device tensor of >= {need} bytes")
     bp = _ptr(b) if b is not None else ctypes.c_void_p(0)
     L.check(L.lib().obfft_mfma_probe(kind, _ptr(a), bp, _ptr(d), _stream(stream)), "obfft_mfma_probe")
     return d

@@ -17,7 +17,8 @@ hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipSt
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
-                              void* out, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
+                              void* out, const uint16_t* phaseA, const CrtConsts* C, const int8_t* phaseA_i8,
+                              const CrtI8Consts* i8, hipStream_t st);
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
@@ -556,6 +557,8 @@ struct CrtCache {
   CrtConsts C;
   uint16_t* d_phaseA = nullptr;
   CrtConsts* d_C = nullptr;
+  int8_t* d_phaseA_i8 = nullptr;  // INT8 Phase-A operand (64 lanes x 16 bytes)
+  CrtI8Consts* d_i8 = nullptr;
 };
 static std::mutex g_crt_mu;
 static std::map<std::pair<int, int>, CrtCache> g_crt;
@@ -581,6 +584,15 @@ static obfft_status_t crt_cache(int precision, CrtCache** out) {
     if (!cc->d_C && hipMalloc(&cc->d_C, sizeof(CrtConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
     if (hipMemcpy(cc->d_C, &cc->C, sizeof(CrtConsts), hipMemcpyHostToDevice) != hipSuccess)
       return OBFFT_HIP_ERROR;
+    CrtI8Consts K;
+    std::vector<int8_t> a8;
+    build_crt_i8(H, cc->C, K, a8);
+    if (!cc->d_phaseA_i8 && hipMalloc(&cc->d_phaseA_i8, a8.size()) != hipSuccess) return OBFFT_ALLOC_FAILED;
+    if (hipMemcpy(cc->d_phaseA_i8, a8.data(), a8.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return OBFFT_HIP_ERROR;
+    if (!cc->d_i8 && hipMalloc(&cc->d_i8, sizeof(CrtI8Consts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
+    if (hipMemcpy(cc->d_i8, &K, sizeof(CrtI8Consts), hipMemcpyHostToDevice) != hipSuccess)
+      return OBFFT_HIP_ERROR;
     cc->ready = true;
   }
   *out = cc;
@@ -605,7 +617,7 @@ extern "C" obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const 
 
 extern "C" obfft_status_t obfft_crt_reconstruct_method(int precision, int method, int64_t n, const void* residues,
                                                        const void* exps, void* out, void* stream) {
-  if ((precision != 0 && precision != 1) || method < OBFFT_CRT_KULISCH || method > OBFFT_CRT_SLICE_FP64 ||
+  if ((precision != 0 && precision != 1) || method < OBFFT_CRT_KULISCH || method > OBFFT_CRT_KULISCH_INT8 ||
       n < 0 || (n > 0 && (!residues || !exps || !out)))
     return OBFFT_INVALID_VALUE;
   if (n >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
@@ -616,7 +628,7 @@ extern "C" obfft_status_t obfft_crt_reconstruct_method(int precision, int method
   obfft_status_t st = crt_cache(precision, &cc);
   if (st != OBFFT_SUCCESS) return st;
   if (launch_crt_ablation(precision, method, n, (const uint16_t*)residues, (const int*)exps, out, cc->d_phaseA,
-                          cc->d_C, (hipStream_t)stream) != hipSuccess)
+                          cc->d_C, cc->d_phaseA_i8, cc->d_i8, (hipStream_t)stream) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;
 }
@@ -637,7 +649,7 @@ extern "C" void obfft_taps_layout(obfft_taps_layout_t* t) {
 // the hardware-contract tests.  kind: 0 fp8 16x16x32, 1 i8 16x16x64,
 // 2 f16 32x32x16, 3 permlane32 swap, 4 E4M3 conversion, 5 f16 16x16x32.
 extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream) {
-  if (kind < 0 || kind > 5 || !a || !d || (kind != 4 && !b)) return OBFFT_INVALID_VALUE;
+  if (kind < 0 || kind > 6 || !a || !d || (kind != 4 && !b)) return OBFFT_INVALID_VALUE;
   if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
   return launch_mfma_probe(kind, a, b, d, (hipStream_t)stream) == hipSuccess ? OBFFT_SUCCESS : OBFFT_HIP_ERROR;
 }

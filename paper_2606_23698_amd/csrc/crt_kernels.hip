@@ -6,7 +6,10 @@
 //    (Sec. 5.1, Alg. 2), with optional checkpoint taps;
 //  * garner_kernel and slice_fp64_kernel: two of the reconstructions the
 //    paper ranks the Kulisch route against (Sec. 4.1, Eq. recursive-garner;
-//    Sec. 4.2 and App. C, the plain FP64 Phase B).
+//    Sec. 4.2 and App. C, the plain FP64 Phase B);
+//  * crt_int8_kernel: the Kulisch route with Phase A moved to the INT8
+//    matrix cores (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq. h1-group).
+#include "crt_methods.h"
 #include "ob_recon.h"
 
 namespace obfft {
@@ -199,6 +202,137 @@ __global__ __launch_bounds__(256) void slice_fp64_kernel(int64_t n, const uint16
     ((float*)out)[o] = (float)y;
 }
 
+// ---- Phase A on INT8 MFMA: two limbs, shifted columns ----
+
+// The B operand of one 32x32x32 INT8 MFMA for output o and lane half h:
+// limb q = 16 h + j of the output, where limbs 0 .. R-1 are the low bytes
+// v0_k = v_k - 256 v1_k (as two's-complement bytes: v_k mod 256) and limbs
+// R .. 2R-1 the high limbs v1_k = (v_k + 128) >> 8 in [0, 8]; zeros beyond,
+// and for o >= n.
+template <int R>
+__device__ __forceinline__ v4i_t limb_operand(const uint16_t* residues, int64_t n, int64_t o, int h) {
+  static_assert(R % 2 == 0 && 2 * R <= 32, "limb layout");
+  uint32_t lo[R], hi[R];
+#pragma unroll
+  for (int k = 0; k < R; k++) lo[k] = hi[k] = 0;
+  if (o < n) {
+    const uint32_t* row = (const uint32_t*)(residues + o * R);
+#pragma unroll
+    for (int k = 0; k < R / 2; k++) {
+      const uint32_t pr = row[k];
+      lo[2 * k] = pr & 0xFFu;
+      lo[2 * k + 1] = (pr >> 16) & 0xFFu;
+      hi[2 * k] = ((pr & 0xFFFFu) + 128u) >> 8;
+      hi[2 * k + 1] = ((pr >> 16) + 128u) >> 8;
+    }
+  }
+  auto limb = [&](int q) -> uint32_t { return q < R ? lo[q] : (q < 2 * R ? hi[q - R] : 0u); };
+  v4i_t b0, b1;
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    b0[w] = (int)(limb(4 * w) | (limb(4 * w + 1) << 8) | (limb(4 * w + 2) << 16) | (limb(4 * w + 3) << 24));
+    b1[w] = (int)(limb(16 + 4 * w) | (limb(17 + 4 * w) << 8) | (limb(18 + 4 * w) << 16) |
+                  (limb(19 + 4 * w) << 24));
+  }
+  return h ? b1 : b0;
+}
+
+// Column j of the Phase-A product after the lane-half swap: rows
+// 8a + b (b < 4) sit in xv[4a + b], rows 8a + 4 + b in yv[4a + b].
+__device__ __forceinline__ uint32_t i8_part(const uint32_t* xv, const uint32_t* yv, int j) {
+  const int a = j >> 3, b = j & 7;
+  return b < 4 ? xv[4 * a + b] : yv[4 * a + b - 4];
+}
+
+// Four biased column sums (each in (0, 2^19)) deposited at bits 0, 8, 16, 24
+// of one word: the low word L and the spill H into the next word.
+__device__ __forceinline__ void i8_column(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t& L,
+                                          uint32_t& H) {
+  uint32_t c1, c2;
+  uint32_t l = b0 + (b1 << 8);
+  l = addc(l, b2 << 16, 0u, &c1);
+  l = addc(l, b3 << 24, 0u, &c2);
+  L = l;
+  H = (b2 >> 16) + (b3 >> 8) + c1 + c2;
+}
+
+// One output per lane, 64 per wave: Phase A as two 32x32x32 INT8 MFMAs (the
+// matrix rows are the S + 2 raw and T + 2 lift columns of balanced-digit
+// slices, the contraction runs over the 2r limbs; INT32 accumulation is
+// exact: |column| <= r 128 136), the accumulators started at the bias; then
+// W = sum_s col_s 256^s + wadd = E + M/2 + zoff M (mod 2^(32 NW)) and
+// zhat + zoff from the lift columns, the exact two-sided lift and the pack.
+template <int TGT>
+__global__ __launch_bounds__(256) void crt_int8_kernel(int64_t n, const uint16_t* residues, const int* exps,
+                                                       void* out, const int8_t* aop_tab, const CrtConsts* crt,
+                                                       const CrtI8Consts* i8) {
+  typedef Tgt<TGT> TT;
+  constexpr int R = TT::R, S = TT::S, NW = TT::NW;
+  typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  if (base >= n) return;
+  const int h = lane >> 5;
+  const v4i_t aop = ((const v4i_t*)aop_tab)[lane];
+  const int64_t o1 = base + (lane & 31), o2 = o1 + 32;
+  const v4i_t b1 = limb_operand<R>(residues, n, o1, h), b2 = limb_operand<R>(residues, n, o2, h);
+  v16i_t seed;
+#pragma unroll
+  for (int v = 0; v < 16; v++) seed[v] = kI8PhaseABias;
+  const v16i_t d1 = mfma_i8_32(aop, b1, seed), d2 = mfma_i8_32(aop, b2, seed);
+  uint32_t xv[16], yv[16];
+#pragma unroll
+  for (int v = 0; v < 16; v++) {
+    auto pr = __builtin_amdgcn_permlane32_swap((uint32_t)d1[v], (uint32_t)d2[v], false, false);
+    xv[v] = pr[0];
+    yv[v] = pr[1];
+  }
+  // raw columns s < S + 2; those at bit 32 NW or above vanish mod 2^(32 NW)
+  constexpr int NS = (S + 2 < 4 * NW) ? S + 2 : 4 * NW;
+  constexpr int NC = (NS + 3) / 4;
+  uint32_t L[NC], H[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    const uint32_t p0 = i8_part(xv, yv, 4 * c);
+    const uint32_t p1 = 4 * c + 1 < NS ? i8_part(xv, yv, 4 * c + 1) : 0u;
+    const uint32_t p2 = 4 * c + 2 < NS ? i8_part(xv, yv, 4 * c + 2) : 0u;
+    const uint32_t p3 = 4 * c + 3 < NS ? i8_part(xv, yv, 4 * c + 3) : 0u;
+    i8_column(p0, p1, p2, p3, L[c], H[c]);
+  }
+  const CrtI8Consts& K = *i8;
+  // two interleaved carry chains: (L + H shifted one word), then + wadd
+  uint32_t W[NW], ca = 0, cb = 0;
+  W[0] = addc(L[0], K.wadd[0], 0u, &cb);
+#pragma unroll
+  for (int i = 1; i < NW; i++) {
+    const uint32_t t = addc(i < NC ? L[i] : 0u, H[i - 1], ca, &ca);
+    W[i] = addc(t, K.wadd[i], cb, &cb);
+  }
+  // lift columns t = 0 .. 7 at rows S + 2 + t: bits 48 .. 63 of their sum
+  // plus zadd (mod 2^64) are zhat + zoff
+  constexpr int Z0 = S + 2;
+  uint32_t ZL0, ZH0, ZL1, ZH1;
+  i8_column(i8_part(xv, yv, Z0), i8_part(xv, yv, Z0 + 1), i8_part(xv, yv, Z0 + 2), i8_part(xv, yv, Z0 + 3), ZL0,
+            ZH0);
+  i8_column(i8_part(xv, yv, Z0 + 4), i8_part(xv, yv, Z0 + 5), i8_part(xv, yv, Z0 + 6), i8_part(xv, yv, Z0 + 7),
+            ZL1, ZH1);
+  (void)ZH1;
+  uint32_t zc;
+  (void)addc(ZL0, K.zadd[0], 0u, &zc);
+  const uint32_t z1 = ZL1 + ZH0 + K.zadd[1] + zc;
+  const uint32_t zh = z1 >> 16;
+  const typename EP::LiftK LK = EP::load_lift(*crt, true);
+  uint32_t Rw[NW];
+  EP::lift_exact(W, zh, LK, Rw);
+  const int64_t o = base + lane;
+  if (o < n) {
+    if (TGT == 0)
+      ((double*)out)[o] = pack_f64<NW>(Rw, exps[o]);
+    else
+      ((float*)out)[o] = pack_f32<NW>(Rw, exps[o]);
+  }
+}
+
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
@@ -212,9 +346,17 @@ hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* e
 }
 
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
-                              void* out, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st) {
+                              void* out, const uint16_t* phaseA, const CrtConsts* C, const int8_t* phaseA_i8,
+                              const CrtI8Consts* i8, hipStream_t st) {
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  if (method == 1) {
+  if (method == 3) {
+    if (tgt == 0)
+      hipLaunchKernelGGL(crt_int8_kernel<0>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, phaseA_i8, C,
+                         i8);
+    else
+      hipLaunchKernelGGL(crt_int8_kernel<1>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, phaseA_i8, C,
+                         i8);
+  } else if (method == 1) {
     if (tgt == 0)
       hipLaunchKernelGGL(garner_kernel<0>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, C);
     else

@@ -612,39 +612,6 @@ __global__ void digits_to_fp8_kernel(uint8_t* p, int64_t n4) {
   ((uint32_t*)p)[i] = o;
 }
 
-// ---- MFMA contract probes (layout and exact integer accumulation) ----
-__global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* d) {
-  const int lane = threadIdx.x;
-  if (kind == 0) {
-    long av = ((const long*)a)[lane], bv = ((const long*)b)[lane];
-    v4f c = {0.f, 0.f, 0.f, 0.f};
-    ((v4f*)d)[lane] = mfma_fp8(av, bv, c);
-  } else if (kind == 1) {
-    v4i av = ((const v4i*)a)[lane], bv = ((const v4i*)b)[lane];
-    v4i c = {0, 0, 0, 0};
-    ((v4i*)d)[lane] = mfma_i8(av, bv, c);
-  } else if (kind == 2) {
-    v8h av = ((const v8h*)a)[lane], bv = ((const v8h*)b)[lane];
-    v16f c;
-    for (int v = 0; v < 16; v++) c[v] = 0.f;
-    ((v16f*)d)[lane] = mfma_f16_32(av, bv, c);
-  } else if (kind == 3) {
-    uint32_t x = ((const uint32_t*)a)[lane], y = ((const uint32_t*)b)[lane];
-    auto pr = __builtin_amdgcn_permlane32_swap(x, y, false, false);
-    ((uint32_t*)d)[lane] = pr[0];
-    ((uint32_t*)d)[64 + lane] = pr[1];
-  } else if (kind == 5) {
-    v8h av = ((const v8h*)a)[lane], bv = ((const v8h*)b)[lane];
-    v4f c = {0.f, 0.f, 0.f, 0.f};
-    ((v4f*)d)[lane] = mfma_f16_16(av, bv, c);
-  } else if (kind == 4) {
-    // E4M3 conversion of small integers: a = 64 floats, d = 64 bytes
-    float x = ((const float*)a)[lane];
-    uint32_t w = fp8_pack2<false>(x, 0.0f, 0u);
-    ((uint8_t*)d)[lane] = (uint8_t)(w & 0xFF);
-  }
-}
-
 // ---- host-side launch helpers ----
 template <int SUB, int TGT, int KMAX, bool FULL>
 static hipError_t launch_stage_t(const StageParams& P, dim3 grid, hipStream_t st) {
@@ -737,11 +704,6 @@ int stage_cols_per_wg(int K) { return K <= 16 ? Shape<16>::NCOL : Shape<32>::NCO
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st) {
   int64_t n4 = bytes / 4;
   hipLaunchKernelGGL(digits_to_fp8_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, p, n4);
-  return hipGetLastError();
-}
-
-hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st) {
-  hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, st, kind, a, b, d);
   return hipGetLastError();
 }
 

@@ -217,6 +217,58 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
   }
 }
 
+// INT8 Phase-A route (Sec. 8.3, Eq. h1-group, on signed bytes).  The A
+// operand is 32 rows x 32 limb columns of int8: row s < S + 2 is raw column s,
+// row S + 2 + t lift column t; column k < r multiplies the low limb of
+// modulus k by the balanced base-256 digit s of u_k, column r + k its high
+// limb by digit s - 1 (the shifted column); lift rows use the digits of w_k.
+// Lane l holds row l % 32, columns 16 (l / 32) .. + 15.
+static void balanced_digits(u128 x, int count, int* d) {
+  for (int i = 0; i < count; i++) {
+    int b = (int)(x & 0xFF);
+    if (b >= 128) b -= 256;
+    d[i] = b;
+    x = (b >= 0 ? x - (u128)b : x + (u128)(-b)) >> 8;
+  }
+  if (x != 0) throw std::runtime_error("balanced digits");
+}
+
+void build_crt_i8(const ModSet& H, const CrtConsts& C, CrtI8Consts& K, std::vector<int8_t>& aop) {
+  const int r = H.r, S = H.S, T = H.T, NW = C.nwords;
+  K.raw = S + 2;
+  K.frac = T + 2;
+  if (K.raw + K.frac > 32 || 2 * r > 32) throw std::runtime_error("int8 phase A shape");
+  int A[32][32];
+  memset(A, 0, sizeof(A));
+  for (int k = 0; k < r; k++) {
+    int du[17], dw[8];
+    balanced_digits(H.u[k], S + 1, du);
+    balanced_digits((u128)H.w[k], T + 1, dw);
+    for (int s = 0; s < S + 2; s++) {
+      A[s][k] = s <= S ? du[s] : 0;
+      A[s][r + k] = s >= 1 ? du[s - 1] : 0;
+    }
+    for (int t = 0; t < T + 2; t++) {
+      A[S + 2 + t][k] = t <= T ? dw[t] : 0;
+      A[S + 2 + t][r + k] = t >= 1 ? dw[t - 1] : 0;
+    }
+  }
+  aop.assign(64 * 16, 0);
+  for (int l = 0; l < 64; l++)
+    for (int j = 0; j < 16; j++) aop[l * 16 + j] = (int8_t)A[l % 32][16 * (l / 32) + j];
+  // bias of every accumulator, weighted by its column position
+  const u128 mask = NW == 4 ? ~(u128)0 : (((u128)1 << (32 * NW)) - 1);
+  u128 braw = 0, bz = 0;
+  for (int s = 0; s < S + 2 && 8 * s < 128; s++) braw += (u128)kI8PhaseABias << (8 * s);
+  for (int t = 0; t < T + 2; t++) bz += (u128)kI8PhaseABias << (8 * t);
+  const u128 wadd = ((H.M >> 1) + H.M * (u128)kLiftOffset - braw) & mask;
+  const u128 zadd = ((((u128)1) << (kFracBits - 1)) + ((u128)kLiftOffset << kFracBits) - bz) &
+                    ((((u128)1) << 64) - 1);
+  for (int i = 0; i < 4; i++) K.wadd[i] = (uint32_t)(wadd >> (32 * i));
+  K.zadd[0] = (uint32_t)zadd;
+  K.zadd[1] = (uint32_t)(zadd >> 32);
+}
+
 // ---- double-double trigonometry ----
 namespace {
 struct DD {

@@ -73,6 +73,36 @@ def test_i8_mfma_16x16x64_layout_and_exactness(gpu):
 
 
 @pytest.mark.parametrize("extreme", [False, True])
+def test_i8_mfma_32x32x32_layout_and_exactness(gpu, extreme):
+    """INT8 Phase-A contract: signed-byte limbs times balanced slices, 32-term
+    sums in INT32, in the lane layout the INT8 reconstruction route assumes."""
+    api = _api()
+    rng = np.random.default_rng(17)
+    A = rng.integers(-128, 128, size=(32, 32))
+    B = rng.integers(-128, 128, size=(32, 32))
+    if extreme:
+        A[:] = -128
+        B[:] = -128
+    a = np.zeros((64, 16), np.int8)
+    b = np.zeros((64, 16), np.int8)
+    for l in range(64):
+        for j in range(16):
+            k = 16 * (l // 32) + j
+            a[l, j] = A[l % 32, k]
+            b[l, j] = B[k, l % 32]
+    d = torch.zeros((64, 16), dtype=torch.int32, device=gpu)
+    api.mfma_probe(6, torch.from_numpy(a).to(gpu), torch.from_numpy(b).to(gpu), d)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    got = np.zeros((32, 32), np.int64)
+    for l in range(64):
+        for v in range(16):
+            row = (v % 4) + 8 * (v // 4) + 4 * (l // 32)
+            got[row, l % 32] = D[l, v]
+    assert np.array_equal(got, A @ B)
+
+
+@pytest.mark.parametrize("extreme", [False, True])
 def test_f16_mfma_32x32x16_layout_and_exactness(gpu, extreme):
     """Phase-A contract: residues <= 2038 times slices <= 255, 16-term sums, plus 2^23."""
     api = _api()

@@ -1,8 +1,9 @@
-"""GPU parity of the reconstruction ablations (recursive Garner, plain FP64 sum).
+"""GPU parity of the reconstruction ablations (recursive Garner, plain FP64 sum,
+Phase A on INT8 MFMA).
 
-Both kernels are compared with oracle.ablation_ref element by element: Garner
-bit for bit (it is exact, so it must also equal the Kulisch route), the FP64
-sum bit for bit as well (the oracle performs the same IEEE binary64 operations
+Every kernel is compared with oracle.ablation_ref element by element: Garner
+and the INT8 route bit for bit (both are exact, so they must also equal the
+Kulisch route), the FP64 sum bit for bit as well (the oracle performs the same IEEE binary64 operations
 in the same order).  Edge cases: ragged n, n = 1, the boundary values of the
 lift, rounding ties, subnormal scaling and a bad method code.
 """
@@ -60,6 +61,23 @@ def test_garner_bit_exact(gpu, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_int8_phase_a_bit_exact(gpu, precision):
+    from paper_2606_23698_amd import api
+    moduli = K.MODULI_FP64 if precision == "fp64" else K.MODULI_FP32
+    target = "f64" if precision == "fp64" else "f32"
+    rng = np.random.default_rng(26)
+    vals = _values(moduli, rng, 600)
+    exps = rng.integers(-170, -40, size=len(vals)).astype(np.int32)
+    exps[:6] = [-104, 0, -52, -1, -1200, -1100]
+    out, res = _run(gpu, moduli, vals, exps, "kulisch_int8", precision)
+    ref = np.array([A.int8_reconstruct(list(map(int, r)), moduli, int(e), target)["y"]
+                    for r, e in zip(res, exps)], dtype=out.dtype)
+    assert out.tobytes() == ref.tobytes()
+    kul, _ = api.crt_reconstruct(torch.from_numpy(res).to(gpu), torch.from_numpy(exps).to(gpu), precision)
+    assert kul.cpu().numpy().tobytes() == out.tobytes()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_slice_fp64_bit_exact(gpu, precision):
     moduli = K.MODULI_FP64 if precision == "fp64" else K.MODULI_FP32
     target = "f64" if precision == "fp64" else "f32"
@@ -78,14 +96,15 @@ def test_ragged_sizes(gpu, n):
     rng = np.random.default_rng(23 + n)
     vals = _values(moduli, rng, 600)[:n]
     exps = np.full(len(vals), -104, dtype=np.int32)
-    for method, fn in (("garner", A.garner_reconstruct), ("slice_fp64", A.slice_fp64)):
+    for method, fn in (("garner", A.garner_reconstruct), ("slice_fp64", A.slice_fp64),
+                       ("kulisch_int8", A.int8_reconstruct)):
         out, res = _run(gpu, moduli, vals, exps, method, "fp64")
         ref = np.array([fn(list(map(int, r)), moduli, -104)["y"] for r in res])
         assert out.tobytes() == ref.tobytes()
 
 
-def test_large_n_garner_equals_kulisch(gpu):
-    """At 2^22 outputs of uniformly random residue tuples the two exact
+def test_large_n_exact_routes_agree(gpu):
+    """At 2^22 outputs of uniformly random residue tuples the three exact
     routes agree everywhere; 512 sampled outputs also match the oracle."""
     from paper_2606_23698_amd import api
     moduli = K.MODULI_FP64
@@ -96,8 +115,10 @@ def test_large_n_garner_equals_kulisch(gpu):
     exps = torch.full((n,), -110, dtype=torch.int32, device=gpu)
     gar = api.crt_reconstruct_method(res, exps, "garner")
     kul = api.crt_reconstruct_method(res, exps, "kulisch")
+    ki8 = api.crt_reconstruct_method(res, exps, "kulisch_int8")
     torch.cuda.synchronize()
     assert torch.equal(gar.view(torch.int64), kul.view(torch.int64))
+    assert torch.equal(ki8.view(torch.int64), kul.view(torch.int64))
     idx = np.random.default_rng(25).choice(n, 512, replace=False)
     rs = res[torch.from_numpy(idx).to(gpu)].cpu().numpy()
     ref = np.array([A.garner_reconstruct(list(map(int, r)), moduli, -110)["y"] for r in rs])
