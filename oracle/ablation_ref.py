@@ -30,6 +30,13 @@ balanced base-256 digits in [-128, 128) (one more digit than the unsigned
 bytes); sum_s 256^s P'_s is still sum_k v_k u_k, so the result is the
 Kulisch route's bit for bit.
 
+A fourth route keeps Phase A and narrows the Kulisch word (Sec. 6.3, Eq.
+kulisch-width; Sec. 6.4, Strategy A and Table substrate): the slice sums
+P_s (below 2^23) are deposited at bit 8s into 16-bit words of radix 2^12
+(four guard bits each), every slice spread over the three words its bits
+touch, and one carry sweep at the end resolves the redundant form.  The
+accumulated integer is the same, so is the output.
+
 Readings where the paper leaves the order open (recorded in the design notes):
 the FP64 sum runs over s = 0, 1, ..., S-1; M enters the FP64 lift as its
 nearest binary64 value and zhat * M is rounded before the subtraction; the
@@ -154,3 +161,43 @@ def int8_reconstruct(v, moduli, exp=0, target="f64"):
     R = crt_ref.two_sided_lift(E, zhat, M)
     y = crt_ref.pack_f64(R, exp) if target == "f64" else crt_ref.pack_f32(R, exp)
     return {"P": P, "Z": Z, "E": E, "zhat": zhat, "R": R, "y": y}
+
+
+RADIX16 = 12   # usable bits of a 16-bit word (four guard bits), Table substrate
+WORDS16 = 11   # 11 x 12 = 132 bits: the accumulator modulo 2^132
+
+
+def kulisch16_deposit(P):
+    """Strategy A: P_s at bit 8s into radix-2^12 words (each < 2^16 before the
+    sweep), then the carry sweep; returns (words before, words after), both
+    modulo 2^132."""
+    mask = (1 << RADIX16) - 1
+    w = [0] * (WORDS16 + 2)
+    for s, ps in enumerate(P):
+        assert 0 <= ps < (1 << 23)
+        q, o = divmod(8 * s, RADIX16)
+        x = ps << o
+        for j in range(3):
+            w[q + j] += (x >> (RADIX16 * j)) & mask
+    raw = w[:WORDS16]
+    assert all(0 <= x < (1 << 16) for x in raw), "guard bits overflowed"
+    out = list(raw)
+    for i in range(WORDS16 - 1):
+        out[i + 1] += out[i] >> RADIX16
+        out[i] &= mask
+    out[-1] &= mask
+    return raw, out
+
+
+def int16_reconstruct(v, moduli, exp=0, target="f64"):
+    """Phase A, the 16-bit-word Kulisch accumulation, the two-sided lift, one pack."""
+    M = K.modulus_product(moduli)
+    P, Z = crt_ref.phase_a(v, moduli)
+    raw, W = kulisch16_deposit(P)
+    # sum_s P_s 256^s <= 4360 M < 2^131 (canonical residues), so the 132-bit
+    # accumulator holds E exactly
+    E = sum(x << (RADIX16 * i) for i, x in enumerate(W))
+    zhat = crt_ref.zhat_from(Z)
+    R = crt_ref.two_sided_lift(E, zhat, M)
+    y = crt_ref.pack_f64(R, exp) if target == "f64" else crt_ref.pack_f32(R, exp)
+    return {"raw": raw, "W": W, "E": E, "zhat": zhat, "R": R, "y": y}

@@ -1,4 +1,4 @@
-"""Pins of the reconstruction-ablation oracle (Garner, plain FP64 sum, INT8 Phase A); no GPU.
+"""Pins of the reconstruction-ablation oracle (Garner, FP64 sum, INT8 Phase A, 16-bit words); no GPU.
 
 Garner is pinned to the mixed-radix representation obtained by repeated
 division (a different computation from the paper's recursion), to textbook
@@ -9,7 +9,9 @@ lift lands far outside it) and to the exact special case of a zero tuple.
 The INT8 Phase A is pinned to the defining identities of its columns
 (sum_s 256^s P'_s = sum_k v_k u_k with the plain u_k, not the byte slices of
 the FP16 route), to their INT32 bound, to hand-worked digit examples and to
-the FP16 route's final values.
+the FP16 route's final values.  The 16-bit-word accumulator is pinned to
+hand-worked deposits with and without a carry, to the plain value
+sum_k v_k u_k and its guard-bit bound, and to the 32-bit route's outputs.
 """
 from fractions import Fraction
 
@@ -145,4 +147,49 @@ def test_int8_route_equals_fp16_route(moduli, target):
         a = A.int8_reconstruct(v, moduli, exp, target)
         b = crt_ref.reconstruct(v, moduli, exp, target)
         assert a["R"] == C == b["R"] and a["zhat"] == b["zhat"]
+        assert np.float64(a["y"]).tobytes() == np.float64(b["y"]).tobytes()
+
+
+# ---- 16-bit Kulisch words, Strategy A (Sec. 6.4) ----
+
+def test_kulisch16_hand_example():
+    # P_0 = 0x5BC123 at bit 0 -> words 0x123, 0x5BC; P_1 = 1 at bit 8 -> 0x100 in word 0
+    raw, W = A.kulisch16_deposit([0x5BC123, 1])
+    assert raw[:3] == [0x123 + 0x100, 0x5BC, 0]
+    assert W[:3] == [0x223, 0x5BC, 0]
+    # P_1 = 0x10 at bit 8 is 0x1000: nothing in word 0, 1 in word 1
+    raw, W = A.kulisch16_deposit([0xFFF, 0x10])
+    assert raw[:2] == [0xFFF, 0x1] and W[:2] == [0xFFF, 0x1]
+    raw, W = A.kulisch16_deposit([0xFFF, 0x1])
+    assert raw[0] == 0xFFF + 0x100 and W[:2] == [0x0FF, 0x1]
+
+
+@pytest.mark.parametrize("moduli", [K.MODULI_FP64, K.MODULI_FP32], ids=["fp64", "fp32"])
+def test_kulisch16_value_and_guard_bits(moduli):
+    """The swept words spell sum_s 256^s P_s exactly and no word overflows its
+    16 bits before the sweep, for extreme and random tuples."""
+    rng = np.random.default_rng(17)
+    U = K.idempotents(moduli)
+    tuples = [[m - 1 for m in moduli], [0] * len(moduli)]
+    tuples += [[int(rng.integers(0, m)) for m in moduli] for _ in range(300)]
+    for v in tuples:
+        P, _ = crt_ref.phase_a(v, moduli)
+        raw, W = A.kulisch16_deposit(P)
+        assert sum(x << (12 * i) for i, x in enumerate(W)) == sum(a * b for a, b in zip(v, U))
+        assert max(raw) < 1 << 16 and all(0 <= x < 1 << 12 for x in W)
+
+
+@pytest.mark.parametrize("moduli,target", [(K.MODULI_FP64, "f64"), (K.MODULI_FP32, "f32")], ids=["fp64", "fp32"])
+def test_int16_route_equals_int32_route(moduli, target):
+    M = K.modulus_product(moduli)
+    h = M // 2
+    rng = np.random.default_rng(18)
+    vals = [0, 1, -1, h - 1, -h, -h + 1, (1 << 53) + 1]
+    vals += [int.from_bytes(rng.bytes(16), "little") % M - h for _ in range(200)]
+    for C in vals:
+        v = [C % m for m in moduli]
+        exp = int(rng.integers(-200, 10))
+        a = A.int16_reconstruct(v, moduli, exp, target)
+        b = crt_ref.reconstruct(v, moduli, exp, target)
+        assert a["R"] == C == b["R"]
         assert np.float64(a["y"]).tobytes() == np.float64(b["y"]).tobytes()
