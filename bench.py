@@ -138,8 +138,8 @@ def batch_throughput(api, inputs, steps):
 
 def crt_methods(api, inputs, steps):
     """The reconstruction ablations on the residues of one real stage: the
-    Kulisch route with Phase A on FP16 and on INT8 MFMA, recursive Garner and
-    the plain FP64 sum, each a standalone kernel that reads the residues from
+    Kulisch route with Phase A on FP16 and on INT8 MFMA and with 16-bit
+    accumulator words, recursive Garner and the plain FP64 sum, each a standalone kernel that reads the residues from
     HBM."""
     import torch
     shape = (256, 256, 256)
@@ -155,13 +155,13 @@ def crt_methods(api, inputs, steps):
                         "256^3 forward FFT (uniform[-1,1) seed 4), exponent 0",
             "n": n, "hbm_floor_ms": round(n * (24 + 4 + 8) / (HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     outs = {}
-    for m in ("kulisch", "kulisch_int8", "garner", "slice_fp64"):
+    for m in ("kulisch", "kulisch_int8", "kulisch_int16", "garner", "slice_fp64"):
         o = torch.empty(n, dtype=torch.float64, device=res.device)
         ms, _ = time_steps(lambda m=m, o=o: api.crt_reconstruct_method(res, exps, m, out=o), steps, 2)
         outs[m] = o
         line[m] = {"ms": round(ms, 4), "ns_per_output": round(ms * 1e6 / n, 5)}
     exact = outs["kulisch"]
-    for m in ("kulisch_int8", "garner"):
+    for m in ("kulisch_int8", "kulisch_int16", "garner"):
         line[m]["bit_identical_to_kulisch"] = bool(torch.equal(outs[m].view(torch.int64), exact.view(torch.int64)))
     d = outs["slice_fp64"] - exact
     nz = exact != 0

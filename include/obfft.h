@@ -182,11 +182,15 @@ enum {
                                scaled by 2^exps[i]; FP32 target: y rounded to binary32.  The
                                accuracy baseline: not exact, it keeps about the top 53 of the
                                sum's ~120 bits. */
-  OBFFT_CRT_KULISCH_INT8 = 3 /* the Kulisch route with Phase A on INT8 MFMA (Sec. 8.2, the B200
+  OBFFT_CRT_KULISCH_INT8 = 3, /* the Kulisch route with Phase A on INT8 MFMA (Sec. 8.2, the B200
                                cross-check; Sec. 8.3, Eq. h1-group): residues split into two
                                signed-byte limbs v = v0 + 256 v1, the high limb against the next
                                lower slice, slices of u_k and w_k as balanced base-256 digits,
                                exact INT32 accumulation.  Same output bits as OBFFT_CRT_KULISCH. */
+  OBFFT_CRT_KULISCH_INT16 = 4 /* the Kulisch accumulator in 16-bit words (Sec. 6.3, Eq.
+                               kulisch-width; Sec. 6.4, Strategy A): slice sums deposited into
+                               radix-2^12 words with four guard bits, one carry sweep at the
+                               end.  Same output bits as OBFFT_CRT_KULISCH. */
 };
 
 /* The standalone reconstruction by one of the methods above, for timing and

@@ -260,11 +260,12 @@ def crt_reconstruct(residues, exps, precision="fp64", taps=False, stream=None):
     return out, tp
 
 
-CRT_METHODS = {"kulisch": 0, "garner": 1, "slice_fp64": 2, "kulisch_int8": 3}
+CRT_METHODS = {"kulisch": 0, "garner": 1, "slice_fp64": 2, "kulisch_int8": 3, "kulisch_int16": 4}
 
 
 def crt_reconstruct_method(residues, exps, method, precision="fp64", out=None, stream=None):
-    """One of the reconstruction methods (kulisch, garner, slice_fp64, kulisch_int8) of n scalars:
+    """One of the reconstruction methods (kulisch, garner, slice_fp64, kulisch_int8,
+    kulisch_int16) of n scalars:
     residues int16 [n, r] (canonical), exps int32 [n]."""
     _check_residues(residues, precision)
     n = residues.shape[0]

@@ -18,7 +18,7 @@ hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* e
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
                               void* out, const uint16_t* phaseA, const CrtConsts* C, const int8_t* phaseA_i8,
-                              const CrtI8Consts* i8, hipStream_t st);
+                              const CrtAltConsts* i8, hipStream_t st);
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
@@ -558,7 +558,7 @@ struct CrtCache {
   uint16_t* d_phaseA = nullptr;
   CrtConsts* d_C = nullptr;
   int8_t* d_phaseA_i8 = nullptr;  // INT8 Phase-A operand (64 lanes x 16 bytes)
-  CrtI8Consts* d_i8 = nullptr;
+  CrtAltConsts* d_i8 = nullptr;
 };
 static std::mutex g_crt_mu;
 static std::map<std::pair<int, int>, CrtCache> g_crt;
@@ -584,14 +584,14 @@ static obfft_status_t crt_cache(int precision, CrtCache** out) {
     if (!cc->d_C && hipMalloc(&cc->d_C, sizeof(CrtConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
     if (hipMemcpy(cc->d_C, &cc->C, sizeof(CrtConsts), hipMemcpyHostToDevice) != hipSuccess)
       return OBFFT_HIP_ERROR;
-    CrtI8Consts K;
+    CrtAltConsts K;
     std::vector<int8_t> a8;
-    build_crt_i8(H, cc->C, K, a8);
+    build_crt_alt(H, cc->C, K, a8);
     if (!cc->d_phaseA_i8 && hipMalloc(&cc->d_phaseA_i8, a8.size()) != hipSuccess) return OBFFT_ALLOC_FAILED;
     if (hipMemcpy(cc->d_phaseA_i8, a8.data(), a8.size(), hipMemcpyHostToDevice) != hipSuccess)
       return OBFFT_HIP_ERROR;
-    if (!cc->d_i8 && hipMalloc(&cc->d_i8, sizeof(CrtI8Consts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
-    if (hipMemcpy(cc->d_i8, &K, sizeof(CrtI8Consts), hipMemcpyHostToDevice) != hipSuccess)
+    if (!cc->d_i8 && hipMalloc(&cc->d_i8, sizeof(CrtAltConsts)) != hipSuccess) return OBFFT_ALLOC_FAILED;
+    if (hipMemcpy(cc->d_i8, &K, sizeof(CrtAltConsts), hipMemcpyHostToDevice) != hipSuccess)
       return OBFFT_HIP_ERROR;
     cc->ready = true;
   }
@@ -617,7 +617,7 @@ extern "C" obfft_status_t obfft_crt_reconstruct(int precision, int64_t n, const 
 
 extern "C" obfft_status_t obfft_crt_reconstruct_method(int precision, int method, int64_t n, const void* residues,
                                                        const void* exps, void* out, void* stream) {
-  if ((precision != 0 && precision != 1) || method < OBFFT_CRT_KULISCH || method > OBFFT_CRT_KULISCH_INT8 ||
+  if ((precision != 0 && precision != 1) || method < OBFFT_CRT_KULISCH || method > OBFFT_CRT_KULISCH_INT16 ||
       n < 0 || (n > 0 && (!residues || !exps || !out)))
     return OBFFT_INVALID_VALUE;
   if (n >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;

@@ -8,7 +8,9 @@
 //    paper ranks the Kulisch route against (Sec. 4.1, Eq. recursive-garner;
 //    Sec. 4.2 and App. C, the plain FP64 Phase B);
 //  * crt_int8_kernel: the Kulisch route with Phase A moved to the INT8
-//    matrix cores (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq. h1-group).
+//    matrix cores (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq. h1-group);
+//  * crt_int16_kernel: the Kulisch accumulator in 16-bit words (Sec. 6.3,
+//    Eq. kulisch-width; Sec. 6.4, Strategy A).
 #include "crt_methods.h"
 #include "ob_recon.h"
 
@@ -265,7 +267,7 @@ __device__ __forceinline__ void i8_column(uint32_t b0, uint32_t b1, uint32_t b2,
 template <int TGT>
 __global__ __launch_bounds__(256) void crt_int8_kernel(int64_t n, const uint16_t* residues, const int* exps,
                                                        void* out, const int8_t* aop_tab, const CrtConsts* crt,
-                                                       const CrtI8Consts* i8) {
+                                                       const CrtAltConsts* i8) {
   typedef Tgt<TGT> TT;
   constexpr int R = TT::R, S = TT::S, NW = TT::NW;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(256) void crt_int8_kernel(int64_t n, const uint16_t
     const uint32_t p3 = 4 * c + 3 < NS ? i8_part(xv, yv, 4 * c + 3) : 0u;
     i8_column(p0, p1, p2, p3, L[c], H[c]);
   }
-  const CrtI8Consts& K = *i8;
+  const CrtAltConsts& K = *i8;
   // two interleaved carry chains: (L + H shifted one word), then + wadd
   uint32_t W[NW], ca = 0, cb = 0;
   W[0] = addc(L[0], K.wadd[0], 0u, &cb);
@@ -333,6 +335,88 @@ __global__ __launch_bounds__(256) void crt_int8_kernel(int64_t n, const uint16_t
   }
 }
 
+// ---- Kulisch accumulation in 16-bit words (Strategy A) ----
+
+// One output per lane after the FP16 Phase A of crt_kernel: the slice sums
+// P_s (below 2^23, the exact differences of the partials and their seeds)
+// are deposited at bit 8 s into 16-bit words of radix 2^12, two words per
+// register; each slice spreads over the three words its bits touch, and a
+// word collects at most four pieces, so it stays below 2^14 and the two
+// words of a register are added by one 32-bit add with no carry between
+// them.  A carry sweep resolves the redundant form into 32-bit words, then
+// the lift and the pack are the 32-bit route's.
+template <int TGT>
+__global__ __launch_bounds__(256) void crt_int16_kernel(int64_t n, const uint16_t* residues, const int* exps,
+                                                        void* out, const uint16_t* phaseA, const CrtConsts* crt,
+                                                        const CrtAltConsts* alt) {
+  const CrtConsts& C = *crt;
+  typedef Tgt<TGT> TT;
+  constexpr int R = TT::R, S = TT::S, NW = TT::NW;
+  typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  if (base >= n) return;
+  const int h = lane >> 5;
+  v8h aop = *(const v8h*)(phaseA + lane * 8);
+  const int64_t o1 = base + (lane & 31), o2 = o1 + 32;
+  const v8h b1 = residue_operand<R>(residues, n, o1, h), b2 = residue_operand<R>(residues, n, o2, h);
+  float xv[EP::NV], yv[EP::NV];
+  phase_a<EP::NV>(aop, b1, b2, phase_a_seed(C.seedT_x, h), xv, yv);
+  // words of radix 2^12 covering the 32 NW bits the lift needs
+  constexpr int NQ = (32 * NW + 11) / 12, NR = (NQ + 1) / 2;
+  uint32_t acc[NR + 1];
+#pragma unroll
+  for (int i = 0; i <= NR; i++) acc[i] = 0;
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const uint32_t p = EP::pbits(xv, yv, s) - __float_as_uint(C.seed_x[s]);
+    const int q = (8 * s) / 12, o = (8 * s) % 12;
+    const uint32_t a0 = (p << o) & 0xFFFu;
+    const uint32_t a1 = (p >> (12 - o)) & 0xFFFu;
+    const uint32_t a2 = p >> (24 - o);
+    if ((q & 1) == 0) {
+      if (q / 2 < NR) acc[q / 2] += a0 | (a1 << 16);
+      if (q / 2 + 1 < NR) acc[q / 2 + 1] += a2;
+    } else {
+      if (q / 2 < NR) acc[q / 2] += a0 << 16;
+      if (q / 2 + 1 < NR) acc[q / 2 + 1] += a1 | (a2 << 16);
+    }
+  }
+  // carry sweep over the NQ words, then the 12-bit digits into 32-bit words
+  uint32_t d[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; i++) d[i] = (i & 1) ? acc[i / 2] >> 16 : acc[i / 2] & 0xFFFFu;
+#pragma unroll
+  for (int i = 0; i + 1 < NQ; i++) {
+    d[i + 1] += d[i] >> 12;
+    d[i] &= 0xFFFu;
+  }
+  uint32_t E[NW];
+#pragma unroll
+  for (int j = 0; j < NW; j++) E[j] = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; i++) {
+    const int bit = 12 * i, j = bit / 32, sh = bit % 32;
+    if (j < NW) E[j] |= d[i] << sh;
+    if (sh > 20 && j + 1 < NW) E[j + 1] |= d[i] >> (32 - sh);
+  }
+  const CrtAltConsts& K = *alt;
+  uint32_t W[NW], cy = 0;
+#pragma unroll
+  for (int j = 0; j < NW; j++) W[j] = addc(E[j], K.kadd[j], cy, &cy);
+  const typename EP::LiftK LK = EP::load_lift(C, true);
+  const uint32_t zh = EP::zhat(xv, yv, LK.zhi);
+  uint32_t Rw[NW];
+  EP::lift_exact(W, zh, LK, Rw);
+  const int64_t o = base + lane;
+  if (o < n) {
+    if (TGT == 0)
+      ((double*)out)[o] = pack_f64<NW>(Rw, exps[o]);
+    else
+      ((float*)out)[o] = pack_f32<NW>(Rw, exps[o]);
+  }
+}
+
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
@@ -347,9 +431,14 @@ hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* e
 
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
                               void* out, const uint16_t* phaseA, const CrtConsts* C, const int8_t* phaseA_i8,
-                              const CrtI8Consts* i8, hipStream_t st) {
+                              const CrtAltConsts* i8, hipStream_t st) {
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  if (method == 3) {
+  if (method == 4) {
+    if (tgt == 0)
+      hipLaunchKernelGGL(crt_int16_kernel<0>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, phaseA, C, i8);
+    else
+      hipLaunchKernelGGL(crt_int16_kernel<1>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, phaseA, C, i8);
+  } else if (method == 3) {
     if (tgt == 0)
       hipLaunchKernelGGL(crt_int8_kernel<0>, dim3(blocks), dim3(256), 0, st, n, residues, exps, out, phaseA_i8, C,
                          i8);

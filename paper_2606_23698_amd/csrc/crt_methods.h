@@ -1,7 +1,8 @@
-// Constants and MFMA helper of the INT8 Phase-A reconstruction route (host and
-// device): Phase A on signed-byte MFMA with the two-limb shifted-column layout
-// (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq. h1-group), followed by the
-// same Kulisch Phase B as the FP16 route.
+// Constants and MFMA helper of the alternative exact reconstruction routes
+// (host and device): Phase A on signed-byte MFMA with the two-limb
+// shifted-column layout (Sec. 8.2, the B200 cross-check; Sec. 8.3, Eq.
+// h1-group), and the Kulisch accumulation in 16-bit words (Sec. 6.3, Eq.
+// kulisch-width; Sec. 6.4, Strategy A).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,11 +16,14 @@ namespace obfft {
 // non-negative value below 2^19.
 constexpr int32_t kI8PhaseABias = 1 << 18;
 
-struct CrtI8Consts {
+struct CrtAltConsts {
+  // INT8 Phase A
   int raw;             // raw columns S + 2 (balanced slices of u_k, shifted high limb)
   int frac;            // lift columns T + 2
   uint32_t wadd[4];    // M/2 + zoff M - sum_s bias 256^s  (mod 2^(32 NW))
   uint32_t zadd[2];    // 2^47 + zoff 2^48 - sum_t bias 256^t  (mod 2^64)
+  // 16-bit Kulisch words: added to the swept accumulator E
+  uint32_t kadd[4];    // M/2 + zoff M  (mod 2^(32 NW))
 };
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));

@@ -233,7 +233,7 @@ static void balanced_digits(u128 x, int count, int* d) {
   if (x != 0) throw std::runtime_error("balanced digits");
 }
 
-void build_crt_i8(const ModSet& H, const CrtConsts& C, CrtI8Consts& K, std::vector<int8_t>& aop) {
+void build_crt_alt(const ModSet& H, const CrtConsts& C, CrtAltConsts& K, std::vector<int8_t>& aop) {
   const int r = H.r, S = H.S, T = H.T, NW = C.nwords;
   K.raw = S + 2;
   K.frac = T + 2;
@@ -267,6 +267,8 @@ void build_crt_i8(const ModSet& H, const CrtConsts& C, CrtI8Consts& K, std::vect
   for (int i = 0; i < 4; i++) K.wadd[i] = (uint32_t)(wadd >> (32 * i));
   K.zadd[0] = (uint32_t)zadd;
   K.zadd[1] = (uint32_t)(zadd >> 32);
+  const u128 kadd = ((H.M >> 1) + H.M * (u128)kLiftOffset) & mask;
+  for (int i = 0; i < 4; i++) K.kadd[i] = (uint32_t)(kadd >> (32 * i));
 }
 
 // ---- double-double trigonometry ----

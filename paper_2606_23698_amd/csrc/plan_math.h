@@ -31,7 +31,7 @@ struct ModSet {
 bool build_modset(const int32_t* mods, int r, ModSet& H, std::string& err);
 double capacity_bits(int64_t Kmax, int kbits);
 void build_crt_consts(const ModSet& H, CrtConsts& C);
-void build_crt_i8(const ModSet& H, const CrtConsts& C, CrtI8Consts& K, std::vector<int8_t>& aop);
+void build_crt_alt(const ModSet& H, const CrtConsts& C, CrtAltConsts& K, std::vector<int8_t>& aop);
 void quantised_roots(int64_t N, int bits, std::vector<int64_t>& out);
 int fp8_digits(int m);
 uint8_t e4m3_encode(int d);

@@ -1,8 +1,8 @@
 """GPU parity of the reconstruction ablations (recursive Garner, plain FP64 sum,
-Phase A on INT8 MFMA).
+Phase A on INT8 MFMA, 16-bit Kulisch words).
 
-Every kernel is compared with oracle.ablation_ref element by element: Garner
-and the INT8 route bit for bit (both are exact, so they must also equal the
+Every kernel is compared with oracle.ablation_ref element by element: Garner,
+the INT8 route and the 16-bit words bit for bit (all are exact, so they must also equal the
 Kulisch route), the FP64 sum bit for bit as well (the oracle performs the same IEEE binary64 operations
 in the same order).  Edge cases: ragged n, n = 1, the boundary values of the
 lift, rounding ties, subnormal scaling and a bad method code.
@@ -78,6 +78,23 @@ def test_int8_phase_a_bit_exact(gpu, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_int16_words_bit_exact(gpu, precision):
+    from paper_2606_23698_amd import api
+    moduli = K.MODULI_FP64 if precision == "fp64" else K.MODULI_FP32
+    target = "f64" if precision == "fp64" else "f32"
+    rng = np.random.default_rng(27)
+    vals = _values(moduli, rng, 600)
+    exps = rng.integers(-170, -40, size=len(vals)).astype(np.int32)
+    exps[:6] = [-104, 0, -52, -1, -1200, -1100]
+    out, res = _run(gpu, moduli, vals, exps, "kulisch_int16", precision)
+    ref = np.array([A.int16_reconstruct(list(map(int, r)), moduli, int(e), target)["y"]
+                    for r, e in zip(res, exps)], dtype=out.dtype)
+    assert out.tobytes() == ref.tobytes()
+    kul, _ = api.crt_reconstruct(torch.from_numpy(res).to(gpu), torch.from_numpy(exps).to(gpu), precision)
+    assert kul.cpu().numpy().tobytes() == out.tobytes()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_slice_fp64_bit_exact(gpu, precision):
     moduli = K.MODULI_FP64 if precision == "fp64" else K.MODULI_FP32
     target = "f64" if precision == "fp64" else "f32"
@@ -97,14 +114,14 @@ def test_ragged_sizes(gpu, n):
     vals = _values(moduli, rng, 600)[:n]
     exps = np.full(len(vals), -104, dtype=np.int32)
     for method, fn in (("garner", A.garner_reconstruct), ("slice_fp64", A.slice_fp64),
-                       ("kulisch_int8", A.int8_reconstruct)):
+                       ("kulisch_int8", A.int8_reconstruct), ("kulisch_int16", A.int16_reconstruct)):
         out, res = _run(gpu, moduli, vals, exps, method, "fp64")
         ref = np.array([fn(list(map(int, r)), moduli, -104)["y"] for r in res])
         assert out.tobytes() == ref.tobytes()
 
 
 def test_large_n_exact_routes_agree(gpu):
-    """At 2^22 outputs of uniformly random residue tuples the three exact
+    """At 2^22 outputs of uniformly random residue tuples the four exact
     routes agree everywhere; 512 sampled outputs also match the oracle."""
     from paper_2606_23698_amd import api
     moduli = K.MODULI_FP64
@@ -116,9 +133,11 @@ def test_large_n_exact_routes_agree(gpu):
     gar = api.crt_reconstruct_method(res, exps, "garner")
     kul = api.crt_reconstruct_method(res, exps, "kulisch")
     ki8 = api.crt_reconstruct_method(res, exps, "kulisch_int8")
+    k16 = api.crt_reconstruct_method(res, exps, "kulisch_int16")
     torch.cuda.synchronize()
     assert torch.equal(gar.view(torch.int64), kul.view(torch.int64))
     assert torch.equal(ki8.view(torch.int64), kul.view(torch.int64))
+    assert torch.equal(k16.view(torch.int64), kul.view(torch.int64))
     idx = np.random.default_rng(25).choice(n, 512, replace=False)
     rs = res[torch.from_numpy(idx).to(gpu)].cpu().numpy()
     ref = np.array([A.garner_reconstruct(list(map(int, r)), moduli, -110)["y"] for r in rs])
