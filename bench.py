@@ -24,6 +24,7 @@ METRIC = "ms per 1024^3 Z2Z FFT, emulated vs native FP64, HBM-roof fraction @≤
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TOPS = 39.3216       # 256 CU x 64 lane-ops/clk x 2.4 GHz
 C_EPI_MIN = 203                # the paper's integer-epilogue ledger, low end, instructions / output
+XGMI_LINK_GBS = 153.0          # one xGMI link of MI355X, per direction
 SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
 # HBM bytes per stage launch at 1024^3 on the FP16 substrate, from the
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters in
@@ -174,6 +175,51 @@ def crt_methods(api, inputs, steps):
     return line
 
 
+def slab_share(api, inputs, steps, P=8, N=1024):
+    """One GPU's share of the N^3 transform on P GPUs under the slab
+    decomposition: the n3 and n2 passes on its (N/P) x N x N slab, then the
+    n1 pass on the transposed slab N x (N/P) x N.  The all-to-all between
+    them needs P GPUs and is not run; its time is estimated from the link
+    rate."""
+    import torch
+
+    def passes(plan, x, y, ws, axes):
+        cur = x
+        for axis in axes:
+            plan.stage(axis, 1, cur, ws)
+            plan.stage(axis, 2, ws, y)
+            cur = y
+
+    out = {}
+    for name, shape, axes in (("local_axes", (N // P, N, N), (2, 1)), ("third_axis", (N, N // P, N), (0,))):
+        plan = api.Plan(shape)
+        x = inputs.device_uniform(shape, 5)
+        y, ws = torch.empty_like(x), torch.empty_like(x)
+        ms, _ = time_steps(lambda: passes(plan, x, y, ws, axes), steps, 1)
+        out[name + "_ms"] = round(ms, 3)
+        del plan, x, y, ws
+        torch.cuda.empty_cache()
+    slab_bytes = 16 * N ** 3 // P
+    out["alltoall_estimate_ms"] = round(slab_bytes / P / (XGMI_LINK_GBS * 1e9) * 1e3, 3)
+    out["per_gpu_ms"] = round(out["local_axes_ms"] + out["third_axis_ms"] + out["alltoall_estimate_ms"], 3)
+    out["workload"] = (f"one GPU's share of {N}^3 on {P} GPUs: n3, n2 passes on {N // P}x{N}x{N}, n1 pass on "
+                       f"{N}x{N // P}x{N} (uniform[-1,1) seed 5); all-to-all estimated at {XGMI_LINK_GBS} GB/s per "
+                       f"link, one {slab_bytes // P >> 20} MiB message per peer")
+    print(f"[bench] slab share P={P}: local {out['local_axes_ms']:.2f} ms, third {out['third_axis_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def copy_bandwidth(x, reps=5):
+    """Device-to-device copy rate of the transform's array (read + write bytes / time)."""
+    import torch
+    y = torch.empty_like(x)
+    ms, _ = time_steps(lambda: y.copy_(x), reps, 1)
+    del y
+    torch.cuda.empty_cache()
+    return 2 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(N, pq, target_s=12.0):
     """The exact-pipeline oracle on a bounded sample of axis passes, scaled to one transform.
 
@@ -216,6 +262,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the FP8 / INT8 / FP32-target sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-transform batched measurement")
     ap.add_argument("--no-crt", action="store_true", help="skip the reconstruction-method comparison")
+    ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU share of the 8-GPU slab decomposition")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the input (a known-size reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -260,8 +307,11 @@ def main():
         del ws_a
     torch.cuda.synchronize()
 
+    copy_gbs = copy_bandwidth(x)
+    print(f"[bench] device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     elems = N ** 3
     roof_ms = 96.0 * elems / (HBM_PEAK_GBS * 1e9) * 1e3
+    copy_roof_ms = 96.0 * elems / (copy_gbs * 1e9) * 1e3
     n_out_launch = 2 * elems
     achieved = C_EPI_MIN * n_out_launch / (stage_ms * 1e-3) / 1e12
     line = {
@@ -285,6 +335,10 @@ def main():
         "hbm_roof_ms": round(roof_ms, 3),
         "hbm_roof_frac": round(roof_ms / ms, 4),
         "native_hbm_roof_frac": round(roof_ms / ms_nat, 4) if ms_nat == ms_nat else None,
+        "copy_GBs": round(copy_gbs, 1),
+        "copy_roof_ms": round(copy_roof_ms, 3),
+        "copy_roof_frac": round(copy_roof_ms / ms, 4),
+        "native_copy_roof_frac": round(copy_roof_ms / ms_nat, 4) if ms_nat == ms_nat else None,
         "rel_l2_emulated_vs_native": diff if diff == diff else None,
         "wall_ms_per_step": round(wall, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
@@ -301,6 +355,8 @@ def main():
         line["batch64"] = batch_throughput(api, inputs, max(2, min(args.steps, 5)))
     if not args.no_crt:
         line["crt_methods"] = crt_methods(api, inputs, max(5, min(args.steps, 10)))
+    if not args.no_slab and N == 1024:
+        line["slab_share_p8"] = slab_share(api, inputs, max(2, min(args.steps, 3)))
     if not args.no_cpu:
         try:
             line["cpu_baseline"] = cpu_baseline(N, (info["p"][2], info["q"][2]))

@@ -65,7 +65,7 @@ def test_wide_range_64cubed_error_against_native(gpu):
 
 
 def test_1024cubed_sampled_lines_bit_exact(gpu):
-    """Eight final-axis output lines at 1024^3 against the oracle's exact pipeline.
+    """Eighteen final-axis output lines at 1024^3 against the oracle's exact pipeline.
 
     Line (k2, k3) along axis 1 depends on every input: the oracle evaluates the
     axis-3 output k3 of all N^2 lines, then the axis-2 output k2 of the N lines
@@ -80,7 +80,9 @@ def test_1024cubed_sampled_lines_bit_exact(gpu):
     xt = inputs.device_uniform(shape, 2, device=gpu)
     y = plan.forward(xt)
     torch.cuda.synchronize()
-    samples = [(0, 5), (17, 5), (511, 5), (1023, 5), (3, 1000), (64, 1000), (700, 1000), (1000, 1000)]
+    samples = [(0, 5), (17, 5), (511, 5), (1023, 5), (256, 5), (900, 5),
+               (3, 1000), (64, 1000), (700, 1000), (1000, 1000), (1, 1000), (513, 1000),
+               (0, 512), (2, 512), (31, 512), (32, 512), (512, 512), (1022, 512)]
     got = {s: y[:, s[0], s[1]].cpu().numpy() for s in samples}
     del y
     x = xt.cpu().numpy()
