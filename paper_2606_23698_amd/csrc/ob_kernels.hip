@@ -340,8 +340,12 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   const int nch16 = (2 * K + 31) >> 5;
 
   // residue records of this lane's outputs (row 16 mt + 4 (lane / 16) + v,
-  // column col, Re / Im): rec[2 v + Re/Im][i / 2], half i % 2 = modulus i
-  v2h rec[8][RS::RV];
+  // column col, Re / Im): rec[2 v + Re/Im][i / 2] packs moduli i (low half)
+  // and i + 1 as FP16.  A pair is packed as soon as its odd modulus is done
+  // and pinned in its register, so the records occupy 8 RV registers instead
+  // of staying live as FP32 until the epilogue reads them.
+  uint32_t rec[8][RS::RV];
+  float rlo[8];  // the even modulus of the pair in progress
 #pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
@@ -506,8 +510,15 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
         rrv[v] = reduce_f32(Dv[v] - Ev[v], mf, imf);
         riv[v] = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
       }
-      rec[2 * v][i >> 1][i & 1] = (_Float16)rrv[v];
-      rec[2 * v + 1][i >> 1][i & 1] = (_Float16)riv[v];
+      if ((i & 1) == 0) {
+        rlo[2 * v] = rrv[v];
+        rlo[2 * v + 1] = riv[v];
+      } else {
+        // exact: |residue| <= m/2 + 2 < 2048
+        rec[2 * v][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v], rrv[v]));
+        rec[2 * v + 1][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v + 1], riv[v]));
+        asm volatile("" : "+v"(rec[2 * v][i >> 1]), "+v"(rec[2 * v + 1][i >> 1]));
+      }
     }
     if (P.dbg_res) {  // canonical residue tap (tests only)
       const int64_t co = col_out[col];
@@ -543,8 +554,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     uint32_t b1w[4] = {0u, 0u, 0u, 0u}, b2w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int k = 0; k < RS::RH; k++) {
-      uint32_t x = __builtin_bit_cast(uint32_t, rec[j][k]);
-      uint32_t y = RS::RH + k < RS::RV ? __builtin_bit_cast(uint32_t, rec[j][RS::RH + k]) : 0u;
+      uint32_t x = rec[j][k];
+      uint32_t y = RS::RH + k < RS::RV ? rec[j][RS::RH + k] : 0u;
       auto pr = __builtin_amdgcn_permlane32_swap(x, y, false, false);
       b1w[k] = pr[0];
       b2w[k] = pr[1];
