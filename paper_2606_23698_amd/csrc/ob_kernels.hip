@@ -517,7 +517,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
         // exact: |residue| <= m/2 + 2 < 2048
         rec[2 * v][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v], rrv[v]));
         rec[2 * v + 1][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v + 1], riv[v]));
-        asm volatile("" : "+v"(rec[2 * v][i >> 1]), "+v"(rec[2 * v + 1][i >> 1]));
+        asm("" : "+v"(rec[2 * v][i >> 1]), "+v"(rec[2 * v + 1][i >> 1]));
       }
     }
     if (P.dbg_res) {  // canonical residue tap (tests only)
