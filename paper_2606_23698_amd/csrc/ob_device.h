@@ -238,11 +238,28 @@ struct Epilogue {
   }
 };
 
-// Correctly rounded |R| 2^e with R given as NW two's-complement words;
-// binary64 result.  Single rounding (Sec. 5.1): the top 64 bits plus a
-// sticky bit are converted by one FP64 fma, whose rounding is exact RNE.
+// Correctly rounded R 2^e with R given as NW two's-complement words;
+// binary64 result.  Single rounding (Sec. 5.1).
+//
+// Common case (four words, |R| >= 2^75, normal result): with R = H 2^64 + L
+// (H signed, |H| < 2^53, L unsigned), L is rounded to odd at 2^21 (cut below
+// 2^21, bit 21 set when anything was cut).  The rounding position of R is
+// at least 2^23, so R and the rounded-to-odd R' lie strictly inside the same
+// interval between consecutive even multiples of 2^21 and round alike; H and
+// the 43-bit L' are exact doubles and one fma H 2^64 + L' rounds R' once.
+// Otherwise the top 64 bits of |R| plus a sticky bit are converted by one
+// fma, and subnormal results are rounded at 2^-1074 in integers.
 template <int NW>
 __device__ __forceinline__ double pack_f64(const uint32_t* R, int e) {
+  if (NW == 4) {
+    const int64_t H = (int64_t)(((uint64_t)R[NW - 1] << 32) | R[NW - 2]);
+    if ((uint64_t)(H + 2048) >= 4096u && e >= -1097) {
+      const uint32_t r0 = (R[0] & ~0x1FFFFFu) | ((R[0] & 0x1FFFFFu) ? 0x200000u : 0u);
+      const double hd = __builtin_fma((double)(int32_t)R[NW - 1], 4294967296.0, (double)R[NW - 2]);
+      const double ld = __builtin_fma((double)R[1], 4294967296.0, (double)r0);
+      return __builtin_ldexp(__builtin_fma(hd, 18446744073709551616.0, ld), e);
+    }
+  }
   uint32_t sm = (uint32_t)((int32_t)R[NW - 1] >> 31);
   uint32_t a[4] = {0, 0, 0, 0};
   uint32_t cy = sm & 1u;
