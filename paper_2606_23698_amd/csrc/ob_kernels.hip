@@ -568,7 +568,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     EP::deposits(xv, yv, LK.khi, wv);
     const uint32_t zh = EP::zhat(xv, yv, LK.zhi);
     uint32_t Rw[TT::NW];
-    EP::lift_capacity(wv, zh, LK, Rw);
+    EP::lift_bounded(wv, zh, LK, Rw);
     typename TT::T y;
     if (TGT == 0)
       y = (typename TT::T)pack_f64<TT::NW>(Rw, ex);

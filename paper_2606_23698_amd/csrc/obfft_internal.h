@@ -43,7 +43,6 @@ struct CrtConsts {
   uint32_t M[4];         // M, little-endian words
   uint32_t Mhalf[4];     // M / 2
   uint32_t negM[4];      // -M mod 2^128
-  int64_t thr;           // capacity lift: |top 64 bits of R| above this means R is off by M
   uint32_t khi_x, khi_c; // added to the top deposit word (exact / capacity)
   uint32_t zhi;          // added to word 1 of the lift sum
   uint32_t zoff;         // multiple of M added to E so that zhat stays unsigned

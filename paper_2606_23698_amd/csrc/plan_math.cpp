@@ -129,10 +129,6 @@ void build_crt_consts(const ModSet& H, CrtConsts& C) {
     C.Mhalf[i] = (uint32_t)(Mh >> (32 * i));
     C.negM[i] = (uint32_t)(nM >> (32 * i));
   }
-  // Capacity lift threshold on the top 64 bits of R: a quarter of M in those
-  // units.  A stage output satisfies |C| < 2^(cap - 1) far below it, a lift
-  // that is off by one multiple of M lands far above it.
-  C.thr = (int64_t)((M >> (32 * (NW - 2))) / 4);
   C.zoff = kLiftOffset;
 
   // Bit patterns of the partials: bits(seed) + P with bits(seed) = kFloatBiasBits
