@@ -129,6 +129,8 @@ static void build_modconsts(const ModSet& H, ModConsts& MC, int substrate) {
     MC.m[i] = H.m[i];
     MC.inv_mf[i] = 1.0f / (float)H.m[i];
     MC.inv_md[i] = 1.0 / (double)H.m[i];
+    MC.mf[i] = (float)H.m[i];
+    MC.md[i] = (double)H.m[i];
     MC.nd[i] = fp8_digits(H.m[i]);
     MC.sub[i] = substrate;
   }
@@ -412,6 +414,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   P.amat_fmax = L.fmax;
   P.amat_chmax = L.chmax;
   P.amat_mt = L.mt;
+  P.amat_bytes = (int64_t)std::max(L.G, 1) * L.g_stride;
   P.phaseA = plan->d_phaseA;
   div_magic(inner, &P.inner_magic, &P.inner_shift);
   div_magic(stage == 1 ? p : q, &P.G_magic, &P.G_shift);

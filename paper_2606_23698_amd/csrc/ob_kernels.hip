@@ -339,6 +339,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   constexpr int kF16FormBytes = CH16 * NT * 1024;
   const int nch16 = (2 * K + 31) >> 5;
 
+  // FP16 planes of this tile's matrix through a buffer resource: a scalar
+  // base and byte count, the per-modulus offset in a scalar register and the
+  // lane's 16 bytes as the vector offset (reads past the planes return 0)
+  const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)amat, 0, (int)min(P.amat_bytes - g * P.amat_g_stride, (int64_t)0x7FFFFFFF), 0x00020000);
   // residue records of this lane's outputs (row 16 mt + 4 (lane / 16) + v,
   // column col, Re / Im): rec[2 v + Re/Im][i / 2] packs moduli i (low half)
   // and i + 1 as FP16.  A pair is packed as soon as its odd modulus is done
@@ -350,8 +355,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
     const ModConsts& MC = *P.mc;
-    const double md = (double)MC.m[i], imd = MC.inv_md[i];
-    const float mf = (float)MC.m[i], imf = MC.inv_mf[i];
+    const double md = MC.md[i], imd = MC.inv_md[i];
+    const float mf = MC.mf[i], imf = MC.inv_mf[i];
     const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
     const uint8_t* amod = amat + i * P.amat_mod_stride;
     // A-operand planes of this modulus, issued before the deconstruction so
@@ -376,8 +381,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
 #pragma unroll
         for (int ch = 0; ch < CH16; ch++)
           if (ch < nch)
-            a16[form][ch] = *(const v8h*)(amod + (((int64_t)form * P.amat_mt + mt) * P.amat_chmax + ch) * 1024 +
-                                          lane * 16);
+            a16[form][ch] = __builtin_bit_cast(
+                v8h, __builtin_amdgcn_raw_buffer_load_b128(
+                         arsrc, (uint32_t)lane * 16u,
+                         (uint32_t)(i * P.amat_mod_stride + ((form * P.amat_mt + mt) * P.amat_chmax + ch) * 1024), 0));
     }
     // ---- deconstruction: residues and digit planes (Sec. 2, Eq. ozaki) ----
     // indices past K (when KQ does not divide K) store zero limbs: the FP16

@@ -65,6 +65,8 @@ struct ModConsts {
   int m[kMaxModuli];
   float inv_mf[kMaxModuli];
   double inv_md[kMaxModuli];
+  float mf[kMaxModuli];   // m as FP32 and FP64 (no conversions in the kernels)
+  double md[kMaxModuli];
   int nd[kMaxModuli];    // digits per residue on the FP8 substrate (2 or 3)
   int sub[kMaxModuli];   // substrate of each modulus
 };
@@ -93,6 +95,7 @@ struct StageParams {
   const uint8_t* amat;  // MFMA A-operand planes of this stage / direction
   int64_t amat_g_stride;  // bytes per group g (0 for stage 1)
   int amat_fmax, amat_chmax, amat_mt;  // layout extents of the planes
+  int64_t amat_bytes;                  // bytes of the planes from amat on (all groups)
   int64_t amat_mod_stride;  // bytes per modulus
   const uint16_t* phaseA;   // 64 lanes x 8 FP16 operand of the Phase-A MFMA
   uint16_t* dbg_res;        // canonical residues tap (may be null)
