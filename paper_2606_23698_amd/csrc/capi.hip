@@ -366,6 +366,10 @@ static void div_magic(int64_t d, uint32_t* magic, uint32_t* shift) {
 
 // The stage kernel's grid for `tiles` tiles: a 1-, 2- or 3-D shape that spells
 // out (column tile, group) without divisions when every extent fits.
+// Groups of one column tile run back to back on one XCD (stage 2 of the
+// contiguous axis): their partial output lines merge in that XCD's L2.
+static const int kGroupBlock = 8;
+
 static dim3 stage_grid(StageParams& P, int64_t tiles) {
   const int64_t kMaxYZ = 65535;
   if (P.stage == 1) {
@@ -379,7 +383,7 @@ static dim3 stage_grid(StageParams& P, int64_t tiles) {
       return dim3((unsigned)P.tiles_per_g, (unsigned)P.G);
     }
   } else {
-    const int64_t T = P.tiles_per_g, G = P.G, GB = (G & 7) == 0 ? 8 : G;
+    const int64_t T = P.tiles_per_g, G = P.G, GB = P.gblock;
     if ((T & 7) == 0 && T / 8 <= kMaxYZ && G / GB <= kMaxYZ) {
       P.grid_mode = 3;
       return dim3((unsigned)(8 * GB), (unsigned)(T / 8), (unsigned)(G / GB));
@@ -441,6 +445,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     int ncw = stage_cols_per_wg(P.K);
     P.tiles_per_g = (int)((P.ncols + ncw - 1) / ncw);
     P.g_minor = inner == 1;
+    P.gblock = (q % kGroupBlock) == 0 ? kGroupBlock : (int)q;
     grid = (int64_t)P.tiles_per_g * q;
   }
 }

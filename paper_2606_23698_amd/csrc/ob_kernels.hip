@@ -196,9 +196,9 @@ __device__ __forceinline__ uint32_t udiv31(uint32_t n, uint32_t magic, uint32_t 
 // stride of q elements; the 8 tiles of one column tile with k2 = 8b .. 8b + 7
 // together fill whole 128-byte lines.  Workgroups go to the 8 XCDs round
 // robin (workgroup w on XCD w % 8), each with its own L2: XCD x takes the
-// column tiles c = 8 j + x, and for one block of 8 groups at a time runs the
-// 8 groups of a column tile back to back, so that the partial lines merge in
-// that L2 while only 8 groups' matrix planes are live in it.
+// column tiles c = 8 j + x, and for one block of gblock groups at a time
+// runs those groups of a column tile back to back, so that the partial lines
+// merge in that L2 while only gblock groups' matrix planes are live in it.
 __device__ __forceinline__ void decode_tile(const StageParams& P, int64_t tile, int64_t& c, int64_t& g) {
   if (P.stage == 1) {
     c = tile;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void decode_tile(const StageParams& P, int64_t tile, 
     c = tile % P.tiles_per_g;
   } else {
     const int64_t T = P.tiles_per_g, G = P.G;
-    const int64_t GB = (G & 7) == 0 ? 8 : G;
+    const int64_t GB = P.gblock;
     if ((T & 7) == 0) {
       const int64_t x = tile & 7, slot = tile >> 3, per_blk = (T >> 3) * GB;
       const int64_t blk = slot / per_blk, rem = slot % per_blk;
@@ -230,13 +230,13 @@ __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int6
     case 1: c = bx; g = 0; break;
     case 2: c = bx; g = by; break;
     case 3: {
-      const int64_t GB = (P.G & 7) == 0 ? 8 : P.G;
+      const int64_t GB = P.gblock;
       c = by * 8 + (bx & 7);
       g = bz * GB + (bx >> 3);
       break;
     }
     case 4: {
-      const int64_t GB = (P.G & 7) == 0 ? 8 : P.G;
+      const int64_t GB = P.gblock;
       c = by;
       g = bz * GB + bx;
       break;

@@ -84,8 +84,9 @@ struct StageParams {
   int G;                // number of column groups (p for stage 1, q for stage 2)
   int stage;
   int tiles_per_g;      // stage 2 only
-  int g_minor;          // stage 2: tile order (0: group-major; 1: blocks of 8 groups
+  int g_minor;          // stage 2: tile order (0: group-major; 1: blocks of gblock groups
                         // of a column tile on one XCD back to back, see stage_tile)
+  int gblock;           // groups per block of the group-minor order (divides G)
   int grid_mode;        // how the stage kernel reads (column tile, group) off blockIdx:
                         // 0 linear index, 1 stage 1 (x), 2 group-major (x, y),
                         // 3 group-minor (8 GB, T / 8, G / GB), 4 group-minor (GB, T, G / GB)
