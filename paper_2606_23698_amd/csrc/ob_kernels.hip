@@ -596,7 +596,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
 }
 
 template <int SUB, int TGT, int KMAX, bool FULL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_FP16 ? 4 : 1))) void ob_stage_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_stage_kernel(
     const StageParams P) {
   int64_t c, g;
   grid_tile(P, c, g);
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
 // whose contraction length falls in this kernel's class.  tmember[t] is the
 // member that owns tile t, descs[d] its stage and first[d] its first tile.
 template <int SUB, int TGT, int KMAX>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_FP16 ? 4 : 1))) void ob_batch_kernel(const StageParams* __restrict__ descs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ first,
                                                             const uint16_t* __restrict__ tmember, int64_t total) {
   const int64_t t = blockIdx.x;
