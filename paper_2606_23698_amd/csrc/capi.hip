@@ -23,7 +23,7 @@ hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
 int stage_cols_per_wg(int K);
-hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* first,
+hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, const int64_t* first,
                         const uint16_t* tmember, int64_t total, hipStream_t st);
 int kclass_of(int K);
 int kclass_kmax(int c);
@@ -71,6 +71,7 @@ struct obfft_plan_s {
   uint16_t* d_tmember = nullptr;      // device: member of every tile, launches concatenated
   int64_t tmember_off[6][5] = {};     // per pass and K class: offset into d_tmember
   int64_t batch_total[6][5] = {};     // per pass and K class: tiles (= grid of that launch)
+  int batch_full[6][5] = {};          // per pass and K class: every member has K = the class's KMAX
   void* batch_ws = nullptr;
   std::vector<size_t> ws_off;
   hipGraph_t graph = nullptr;
@@ -735,11 +736,14 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     }
     for (int c = 0; c < 5; c++) {
       int64_t acc = 0;
+      int full = 1;
       for (int i = 0; i < count; i++) {
         if (cls[pass * count + i] != c) continue;
         first[pass * count + i] = acc;
         acc += tiles[pass * count + i];
+        full &= bp->h_desc[pass * count + i].K == kclass_kmax(c);
       }
+      bp->batch_full[pass][c] = full;
       bp->batch_total[pass][c] = acc;
       if (acc >= kMaxTiles) {
         obfft_plan_destroy(bp);
@@ -780,7 +784,8 @@ static obfft_status_t batch_launch_passes(obfft_plan_t bp, hipStream_t st) {
     for (int c = 0; c < 5; c++) {
       int64_t total = bp->batch_total[pass][c];
       if (total <= 0) continue;
-      if (launch_batch(bp->substrate, kclass_kmax(c), bp->d_desc + pass * count, bp->d_first + pass * count,
+      if (launch_batch(bp->substrate, kclass_kmax(c), bp->batch_full[pass][c] != 0, bp->d_desc + pass * count,
+                       bp->d_first + pass * count,
                        bp->d_tmember + bp->tmember_off[pass][c], total, st) != hipSuccess)
         return OBFFT_HIP_ERROR;
     }

@@ -170,7 +170,8 @@ struct Epilogue {
     uint32_t M[NW], Mhalf[NW];
     uint32_t khi, zhi;
   };
-  __device__ __forceinline__ static LiftK load_lift(const CrtConsts& C, bool exact) {
+  template <class CC>  // CrtConsts in any address space
+  __device__ __forceinline__ static LiftK load_lift(const CC& C, bool exact) {
     LiftK k;
 #pragma unroll
     for (int i = 0; i < NW; i++) {

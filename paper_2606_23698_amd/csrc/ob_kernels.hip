@@ -184,8 +184,17 @@ __device__ __forceinline__ void put_limbs16(unsigned char* form_base, int jc, in
 // space after inlining.
 extern __shared__ __align__(16) unsigned char smem[];
 
-// FULL: the contraction length equals KMAX (the common 16 x 16, 16 x 32 and
-// 32 x 32 splits), so every bound on K is known when compiling.
+// FULL: the contraction length equals KMAX (K = 8, 12, 16 or 32 on the FP16
+// substrate: every power-of-two split from 64 on and the 12-point factors of
+// 96 and 192), so every bound on K is known when compiling.
+// Pointers read from a descriptor in memory (the batched launch) are
+// generic to the compiler: every access through them would be a flat access
+// and every constant a vector load.  The stage body therefore reads and
+// writes through pointers typed with their address space: global (1) for
+// data, constant (4) for the plan's read-only tables (scalar loads).
+#define OB_GLOBAL __attribute__((address_space(1)))
+#define OB_CONST __attribute__((address_space(4)))
+
 // n / d for n < 2^31 by a multiply-high with the plan's magic number.
 __device__ __forceinline__ uint32_t udiv31(uint32_t n, uint32_t magic, uint32_t shift) {
   return magic ? (__umulhi(n, magic) >> shift) : n;
@@ -302,7 +311,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     int s = part * KQ + u;
     double xr = 0.0, xi = 0.0;
     if (cin >= 0 && s < K) {
-      typename TT::T2 v = ((const typename TT::T2*)P.in)[cin + (int64_t)s * P.s_in_s];
+      const typename TT::V2 v = ((const OB_GLOBAL typename TT::V2*)P.in)[cin + (int64_t)s * P.s_in_s];
       xr = (double)v.x;
       xi = (double)v.y;
     }
@@ -354,7 +363,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
 #pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
-    const ModConsts& MC = *P.mc;
+    const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)P.mc;
     const double md = MC.md[i], imd = MC.inv_md[i];
     const float mf = MC.mf[i], imf = MC.inv_mf[i];
     const int nd = (SUB == SUB_FP8) ? MC.nd[i] : 2;
@@ -534,8 +543,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
         const int row = 16 * mt + 4 * (lane >> 4) + v;
         if (co >= 0 && row < K) {
           int64_t el = co + (int64_t)row * P.s_out_t;
-          P.dbg_res[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
-          P.dbg_res[(el * 2 + 1) * R + i] = (uint16_t)(riv[v] < 0.0f ? riv[v] + mf : riv[v]);
+          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
+          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2 + 1) * R + i] = (uint16_t)(riv[v] < 0.0f ? riv[v] + mf : riv[v]);
         }
       }
     }
@@ -547,8 +556,8 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   // part.  The low lane half feeds moduli 0 .. ML-1 of its record and the
   // high half moduli ML .. r-1; one swap per packed pair hands each half the
   // other half's share (b1: the low lanes' outputs, b2: the high lanes').
-  const v8h aop = *(const v8h*)(P.phaseA + lane * 8);
-  const CrtConsts& C = *P.crt;
+  const v8h aop = *(const OB_GLOBAL v8h*)(P.phaseA + lane * 8);
+  const OB_CONST CrtConsts& C = *(const OB_CONST CrtConsts*)P.crt;
   const v16f seed = phase_a_seed(C.seedT_c, lane >> 5);
   const typename EP::LiftK LK = EP::load_lift(C, false);
   const int64_t co = col_out[col];
@@ -586,10 +595,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     } else {
       const int row = 16 * mt + 4 * (lane >> 4) + v;
       if (co >= 0 && row < K) {
-        typename TT::T2 z;
+        typename TT::V2 z;
         z.x = re_part;
         z.y = y;
-        ((typename TT::T2*)P.out)[co + (int64_t)row * P.s_out_t] = z;
+        ((OB_GLOBAL typename TT::V2*)P.out)[co + (int64_t)row * P.s_out_t] = z;
       }
     }
   }
@@ -606,7 +615,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
 // Batched stage: one workgroup per tile of the members of one Bailey pass
 // whose contraction length falls in this kernel's class.  tmember[t] is the
 // member that owns tile t, descs[d] its stage and first[d] its first tile.
-template <int SUB, int TGT, int KMAX>
+template <int SUB, int TGT, int KMAX, bool FULL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ first,
                                                             const uint16_t* __restrict__ tmember, int64_t total) {
@@ -616,7 +625,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
   const StageParams P = descs[d];
   int64_t c, g;
   decode_tile(P, t - first[d], c, g);
-  stage_tile<SUB, TGT, KMAX>(P, c, g);
+  stage_tile<SUB, TGT, KMAX, FULL>(P, c, g);
 }
 
 // ---- plan-time conversion of signed digit planes to E4M3 ----
@@ -652,8 +661,14 @@ template <int SUB, int TGT>
 static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st) {
   int K = P.K;
   if (K <= 4) return launch_stage_t<SUB, TGT, 4, false>(P, grid, st);
-  if (K <= 8) return launch_stage_t<SUB, TGT, 8, false>(P, grid, st);
-  if (K <= 12) return launch_stage_t<SUB, TGT, 12, false>(P, grid, st);
+  if (K <= 8) {
+    if (SUB == SUB_FP16 && K == 8) return launch_stage_t<SUB, TGT, 8, SUB == SUB_FP16>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 8, false>(P, grid, st);
+  }
+  if (K <= 12) {
+    if (SUB == SUB_FP16 && K == 12) return launch_stage_t<SUB, TGT, 12, SUB == SUB_FP16>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 12, false>(P, grid, st);
+  }
   if (K <= 16) {
     if (SUB == SUB_FP16 && K == 16) return launch_stage_t<SUB, TGT, 16, SUB == SUB_FP16>(P, grid, st);
     return launch_stage_t<SUB, TGT, 16, false>(P, grid, st);
@@ -673,19 +688,19 @@ hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipSt
                   : launch_stage_k<SUB_FP8, 1>(P, grid, st);
 }
 
-template <int SUB, int KMAX>
+template <int SUB, int KMAX, bool FULL>
 static hipError_t launch_batch_t(const StageParams* descs, const int64_t* first, const uint16_t* tmember,
                                  int64_t total, hipStream_t st) {
   int lds = StageLds<SUB, 0, KMAX>::bytes(KMAX);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_batch_kernel<SUB, 0, KMAX>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_batch_kernel<SUB, 0, KMAX, FULL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX>), dim3((unsigned)total), dim3(kThreads), lds, st, descs, first,
-                     tmember, total);
+  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX, FULL>), dim3((unsigned)total), dim3(kThreads), lds, st, descs,
+                     first, tmember, total);
   return hipGetLastError();
 }
 
@@ -697,24 +712,35 @@ int kclass_kmax(int c) {
   return kmax[c];
 }
 
+// full: every member of the launch has K equal to the class's KMAX (the
+// FP16 substrate then takes the full-length variant).
 template <int SUB>
-static hipError_t launch_batch_s(int kmax, const StageParams* descs, const int64_t* first, const uint16_t* tmember,
-                                 int64_t total, hipStream_t st) {
+static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, const int64_t* first,
+                                 const uint16_t* tmember, int64_t total, hipStream_t st) {
+  constexpr bool F = SUB == SUB_FP16;
   switch (kmax) {
-    case 4: return launch_batch_t<SUB, 4>(descs, first, tmember, total, st);
-    case 8: return launch_batch_t<SUB, 8>(descs, first, tmember, total, st);
-    case 12: return launch_batch_t<SUB, 12>(descs, first, tmember, total, st);
-    case 16: return launch_batch_t<SUB, 16>(descs, first, tmember, total, st);
-    default: return launch_batch_t<SUB, 32>(descs, first, tmember, total, st);
+    case 4: return launch_batch_t<SUB, 4, false>(descs, first, tmember, total, st);
+    case 8:
+      return F && full ? launch_batch_t<SUB, 8, F>(descs, first, tmember, total, st)
+                       : launch_batch_t<SUB, 8, false>(descs, first, tmember, total, st);
+    case 12:
+      return F && full ? launch_batch_t<SUB, 12, F>(descs, first, tmember, total, st)
+                       : launch_batch_t<SUB, 12, false>(descs, first, tmember, total, st);
+    case 16:
+      return F && full ? launch_batch_t<SUB, 16, F>(descs, first, tmember, total, st)
+                       : launch_batch_t<SUB, 16, false>(descs, first, tmember, total, st);
+    default:
+      return F && full ? launch_batch_t<SUB, 32, F>(descs, first, tmember, total, st)
+                       : launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
   }
 }
 
 // FP64-target batched launch over the members of one pass and K class.
-hipError_t launch_batch(int sub, int kmax, const StageParams* descs, const int64_t* first, const uint16_t* tmember,
-                        int64_t total, hipStream_t st) {
-  if (sub == SUB_FP16) return launch_batch_s<SUB_FP16>(kmax, descs, first, tmember, total, st);
-  if (sub == SUB_INT8) return launch_batch_s<SUB_INT8>(kmax, descs, first, tmember, total, st);
-  return launch_batch_s<SUB_FP8>(kmax, descs, first, tmember, total, st);
+hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, const int64_t* first,
+                        const uint16_t* tmember, int64_t total, hipStream_t st) {
+  if (sub == SUB_FP16) return launch_batch_s<SUB_FP16>(kmax, full, descs, first, tmember, total, st);
+  if (sub == SUB_INT8) return launch_batch_s<SUB_INT8>(kmax, false, descs, first, tmember, total, st);
+  return launch_batch_s<SUB_FP8>(kmax, false, descs, first, tmember, total, st);
 }
 
 // Columns per workgroup of the stage kernel for contraction length K.

@@ -15,12 +15,14 @@ template <>
 struct Tgt<0> {
   typedef double T;
   typedef double2 T2;
+  typedef double V2 __attribute__((ext_vector_type(2)));  // one complex value as a plain vector
   static constexpr int PREC = 53, R = 12, S = 15, TZ = 6, NW = 4;
 };
 template <>
 struct Tgt<1> {
   typedef float T;
   typedef float2 T2;
+  typedef float V2 __attribute__((ext_vector_type(2)));
   static constexpr int PREC = 24, R = 6, S = 8, TZ = 6, NW = 3;
 };
 
@@ -54,17 +56,12 @@ __device__ __forceinline__ void phase_a(v8h aop, v8h b1, v8h b2, const v16f& see
 // Accumulator seeds of the Phase-A MFMA: register v of lane half h holds
 // partial 2v + h, seeded with tbl[h][v] (1.5 * 2^23 plus the folded lift
 // constants of that slice).
-__device__ __forceinline__ v16f phase_a_seed(const float (*tbl)[16], int h) {
+template <class TBL>  // float [2][16] in any address space
+__device__ __forceinline__ v16f phase_a_seed(const TBL& tbl, int h) {
   v16f c;
-  const float4* row = (const float4*)tbl[h];
+  const auto* row = &tbl[h][0];
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const float4 f = row[q];
-    c[4 * q] = f.x;
-    c[4 * q + 1] = f.y;
-    c[4 * q + 2] = f.z;
-    c[4 * q + 3] = f.w;
-  }
+  for (int q = 0; q < 16; q++) c[q] = row[q];
   // opaque to the optimiser: the seed stays resident in 16 VGPRs instead of
   // being rematerialised before every MFMA
   asm volatile("" : "+v"(c));
