@@ -293,9 +293,17 @@ __device__ __forceinline__ double pack_f64(const uint32_t* R, int e) {
   return sm ? -r : r;
 }
 
-// binary32 result; |R| < 2^63 (the FP32 modulus set has log2 M = 62.6).
+// binary32 result; |R| < 2^63 (the FP32 modulus set has log2 M = 62.6), so
+// word 2 only repeats the sign of word 1.  Common case |R| >= 2^40: the
+// rounding position is at least 2^17, R rounded to odd at 2^15 is an exact
+// double (48 bits), and one conversion to binary32 rounds it as it would R.
 template <int NW>
 __device__ __forceinline__ float pack_f32(const uint32_t* R, int e) {
+  if (NW == 3 && R[1] + 256u >= 512u && e >= -1000) {
+    const uint32_t r0 = (R[0] & ~0x7FFFu) | ((R[0] & 0x7FFFu) ? 0x8000u : 0u);
+    const double d = __builtin_fma((double)(int32_t)R[1], 4294967296.0, (double)r0);
+    return (float)__builtin_ldexp(d, e);
+  }
   uint32_t sm = (uint32_t)((int32_t)R[NW - 1] >> 31);
   uint32_t a[NW];
   uint32_t cy = sm & 1u;
