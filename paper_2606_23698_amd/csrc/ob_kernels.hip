@@ -298,7 +298,12 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     col_in[tid] = ci;
     col_out[tid] = co;
   }
-  for (int x = tid * 16; x < 2 * DIG; x += kThreads * 16) *(uint4*)(smem + x) = make_uint4(0, 0, 0, 0);
+  // Digit slots that no index writes must read as zero (the FP16 planes must
+  // not meet stale NaN patterns even against zero matrix slots).  Only the
+  // full-length K = 32 tile writes every slot it reads (two limb chunks, or
+  // the whole single-slot chunk, for all its columns), so it skips this.
+  if (!(FULL && KMAX == 32))
+    for (int x = tid * 16; x < 2 * DIG; x += kThreads * 16) *(uint4*)(smem + x) = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----

@@ -58,6 +58,7 @@ def test_forward_32cubed_bit_exact(gpu, substrate):
     ((3, 5, 7), None),                        # 1 x 3, 1 x 5, 1 x 7
     ((1, 1, 1), None),                        # the identity
     ((18, 4, 2), ((3, 6), (1, 4), (2, 1))),   # forced odd / unit factors
+    ((96, 4, 48), ((8, 12), (2, 2), (4, 12))),  # full-length K = 12 and K = 8 launches
 ])
 @pytest.mark.parametrize("substrate", ["fp8", "fp16"])
 def test_forward_small_shapes_bit_exact(gpu, shape, pq, substrate):
