@@ -365,6 +365,46 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   // of staying live as FP32 until the epilogue reads them.
   uint32_t rec[8][RS::RV];
   float rlo[8];  // the even modulus of the pair in progress
+  // Combine of modulus i: centred residues of the GEMM sums into the records.
+  auto combine = [&](const int i, const float* Dv, const float* Ev, const float* Fv, const float mf,
+                     const float imf) {
+    // ---- residue-domain combines, centred residues to the records ----
+    // (Alg. 1 combines; the Phase-A carrier takes them signed, |v| <= m/2 + 2.
+    // Rows past K hold zero products and are never stored.)
+    float rrv[4], riv[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      if (SUB != SUB_FP8) {
+        rrv[v] = reduce_f32(Dv[v], mf, imf);
+        riv[v] = reduce_f32(Fv[v], mf, imf);
+      } else {
+        rrv[v] = reduce_f32(Dv[v] - Ev[v], mf, imf);
+        riv[v] = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
+      }
+      if ((i & 1) == 0) {
+        rlo[2 * v] = rrv[v];
+        rlo[2 * v + 1] = riv[v];
+      } else {
+        // exact: |residue| <= m/2 + 2 < 2048
+        rec[2 * v][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v], rrv[v]));
+        rec[2 * v + 1][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v + 1], riv[v]));
+        asm("" : "+v"(rec[2 * v][i >> 1]), "+v"(rec[2 * v + 1][i >> 1]));
+      }
+    }
+    if (P.dbg_res) {  // canonical residue tap (tests only)
+      const int64_t co = col_out[col];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = 16 * mt + 4 * (lane >> 4) + v;
+        if (co >= 0 && row < K) {
+          int64_t el = co + (int64_t)row * P.s_out_t;
+          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
+          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2 + 1) * R + i] = (uint16_t)(riv[v] < 0.0f ? riv[v] + mf : riv[v]);
+        }
+      }
+    }
+  };
+  float pD[4] = {}, pE[4] = {}, pF[4] = {}, pmf = 1.0f, pimf = 1.0f;  // the GEMM sums awaiting their combine
 #pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
@@ -446,6 +486,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
         put_slots16<KQ, NT>(dig + kF16FormBytes, jc, s0, rb16);
       }
     }
+    if (i > 0 && mt_active) combine(i - 1, pD, pE, pF, pmf, pimf);
     __syncthreads();
     if (!mt_active) continue;
     // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) ----
@@ -518,42 +559,18 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
         Fv[v] = (float)(f - d - e);      // I
       }
     }
-    // ---- residue-domain combines, centred residues to the records ----
-    // (Alg. 1 combines; the Phase-A carrier takes them signed, |v| <= m/2 + 2.
-    // Rows past K hold zero products and are never stored.)
-    float rrv[4], riv[4];
+    // the combine of this modulus runs after the next one's deconstruction,
+    // so the GEMM's latency is covered by independent vector work
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      if (SUB != SUB_FP8) {
-        rrv[v] = reduce_f32(Dv[v], mf, imf);
-        riv[v] = reduce_f32(Fv[v], mf, imf);
-      } else {
-        rrv[v] = reduce_f32(Dv[v] - Ev[v], mf, imf);
-        riv[v] = reduce_f32((Fv[v] - Dv[v]) - Ev[v], mf, imf);
-      }
-      if ((i & 1) == 0) {
-        rlo[2 * v] = rrv[v];
-        rlo[2 * v + 1] = riv[v];
-      } else {
-        // exact: |residue| <= m/2 + 2 < 2048
-        rec[2 * v][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v], rrv[v]));
-        rec[2 * v + 1][i >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rlo[2 * v + 1], riv[v]));
-        asm("" : "+v"(rec[2 * v][i >> 1]), "+v"(rec[2 * v + 1][i >> 1]));
-      }
+      pD[v] = Dv[v];
+      pE[v] = Ev[v];
+      pF[v] = Fv[v];
     }
-    if (P.dbg_res) {  // canonical residue tap (tests only)
-      const int64_t co = col_out[col];
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int row = 16 * mt + 4 * (lane >> 4) + v;
-        if (co >= 0 && row < K) {
-          int64_t el = co + (int64_t)row * P.s_out_t;
-          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
-          ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2 + 1) * R + i] = (uint16_t)(riv[v] < 0.0f ? riv[v] + mf : riv[v]);
-        }
-      }
-    }
+    pmf = mf;
+    pimf = imf;
   }
+  if (mt_active) combine(R - 1, pD, pE, pF, pmf, pimf);
   if (!mt_active) return;
 
   // ---- Phase A (FP16 MFMA) + Phase B (Kulisch, lift, pack) ----
