@@ -34,7 +34,7 @@ constexpr int kFp16Split[2] = {4, 3};
 // keeps zhat unsigned for centred residues, and M / 2 for the exact lift.
 // Whatever does not fit in the last slice's 16 bits is added to the top word
 // (khi, zhi).  Two seed sets: `x` for the exact two-sided lift, `c` for the
-// capacity lift of the stage kernels (no M / 2).
+// lift of the stage kernels under the capacity bound (no M / 2).
 struct CrtConsts {
   int r;                 // number of moduli
   int S;                 // byte slices of u_k
@@ -43,11 +43,11 @@ struct CrtConsts {
   uint32_t M[4];         // M, little-endian words
   uint32_t Mhalf[4];     // M / 2
   uint32_t negM[4];      // -M mod 2^128
-  uint32_t khi_x, khi_c; // added to the top deposit word (exact / capacity)
+  uint32_t khi_x, khi_c; // added to the top deposit word (exact / bounded lift)
   uint32_t zhi;          // added to word 1 of the lift sum
   uint32_t zoff;         // multiple of M added to E so that zhat stays unsigned
   float seed_x[32];      // Phase-A accumulator seeds per partial, exact lift
-  float seed_c[32];      // same, capacity lift
+  float seed_c[32];      // same, bounded lift
   float seedT_x[2][16];  // seed_x[2 v + h] at [h][v]: one lane half's registers
   float seedT_c[2][16];  // same for seed_c
   uint32_t Bp5[5];       // sum_s bits(seed_x[s]) 256^s mod 2^160 (debug taps only)
