@@ -37,6 +37,15 @@ P_s (below 2^23) are deposited at bit 8s into 16-bit words of radix 2^12
 touch, and one carry sweep at the end resolves the redundant form.  The
 accumulated integer is the same, so is the output.
 
+The fifth ablation sits before the reconstruction, in the residue reduction
+of the GEMM sums (Sec. 2, the reduction-friendly moduli; rung H0 of the
+co-design ladder, Sec. 8.3): for m = 2^b - c with a small complement c, an
+integer t = 2^b h + l (h = floor(t / 2^b), l = t mod 2^b) is congruent to
+c h + l, so repeated folds shrink t until one conditional subtraction leaves
+the centred residue; m = 2^b needs only its low b bits.  Residues are unique,
+so this changes no output; the oracle states the steps so that their count
+and range can be checked.
+
 Readings where the paper leaves the order open (recorded in the design notes):
 the FP64 sum runs over s = 0, 1, ..., S-1; M enters the FP64 lift as its
 nearest binary64 value and zhat * M is rounded before the subtraction; the
@@ -201,3 +210,34 @@ def int16_reconstruct(v, moduli, exp=0, target="f64"):
     R = crt_ref.two_sided_lift(E, zhat, M)
     y = crt_ref.pack_f64(R, exp) if target == "f64" else crt_ref.pack_f32(R, exp)
     return {"raw": raw, "W": W, "E": E, "zhat": zhat, "R": R, "y": y}
+
+
+# ---- H0: fold-and-add reduction of the friendly moduli (Sec. 2, Sec. 8.3) ----
+
+H0_MAX_COMPLEMENT = 31  # friendly: 2^b - m <= 31 (the FP64 set's seven have <= 25; 961 has 63)
+
+
+def h0_form(m):
+    """(b, c) with m = 2^b - c, 2^(b-1) < m <= 2^b, when m is friendly; else None."""
+    b = (m - 1).bit_length()
+    c = (1 << b) - m
+    return (b, c) if c <= H0_MAX_COMPLEMENT else None
+
+
+def h0_reduce(t, m):
+    """Centred residue of the integer t by folds, and the number of folds.
+
+    Folds t <- c floor(t / 2^b) + (t mod 2^b) until t lies in
+    [-c, 2^b - 1 + c], then subtracts m once when t >= m - floor(m/2).  For
+    m = 2^b the residue is t mod 2^b taken in [-2^(b-1), 2^(b-1)).
+    """
+    b, c = h0_form(m)
+    B = 1 << b
+    if c == 0:
+        r = t % B
+        return (r - B if r >= B // 2 else r), 0
+    folds = 0
+    while not (-c <= t <= B - 1 + c):
+        t = c * (t // B) + t % B
+        folds += 1
+    return (t - m if t >= m - m // 2 else t), folds

@@ -1,4 +1,4 @@
-"""Pins of the reconstruction-ablation oracle (Garner, FP64 sum, INT8 Phase A, 16-bit words); no GPU.
+"""Pins of the ablation oracle (Garner, FP64 sum, INT8 Phase A, 16-bit words, H0 folds); no GPU.
 
 Garner is pinned to the mixed-radix representation obtained by repeated
 division (a different computation from the paper's recursion), to textbook
@@ -12,6 +12,9 @@ the FP16 route), to their INT32 bound, to hand-worked digit examples and to
 the FP16 route's final values.  The 16-bit-word accumulator is pinned to
 hand-worked deposits with and without a carry, to the plain value
 sum_k v_k u_k and its guard-bit bound, and to the 32-bit route's outputs.
+The H0 fold-and-add reduction is pinned to the paper's list of friendly
+moduli, to hand-worked folds and to the definition of the centred residue
+(congruence and range) over the whole range of the GEMM sums.
 """
 from fractions import Fraction
 
@@ -193,3 +196,36 @@ def test_int16_route_equals_int32_route(moduli, target):
         b = crt_ref.reconstruct(v, moduli, exp, target)
         assert a["R"] == C == b["R"]
         assert np.float64(a["y"]).tobytes() == np.float64(b["y"]).tobytes()
+
+
+# ---- H0 fold-and-add reduction of the friendly moduli (Sec. 2, Sec. 8.3) ----
+
+def test_h0_friendly_set_is_the_papers_seven():
+    friendly = [m for m in K.MODULI_FP64 if A.h0_form(m) is not None]
+    assert sorted(friendly) == [487, 491, 511, 1024, 2027, 2029, 2039]
+    assert A.h0_form(2039) == (11, 9) and A.h0_form(487) == (9, 25) and A.h0_form(1024) == (10, 0)
+
+
+def test_h0_hand_examples():
+    # 2^24 = 8192 * 2^11 -> 9 * 8192 = 73728 = 36 * 2^11 -> 9 * 36 = 324 (2^24 mod 2039 = 324)
+    assert A.h0_reduce(1 << 24, 2039) == (324, 2)
+    # 5000 mod 1024 = 904 -> centred 904 - 1024 = -120, no fold
+    assert A.h0_reduce(5000, 1024) == (-120, 0)
+    # 1500 >= 2039 - 1019: one subtraction, no fold
+    assert A.h0_reduce(1500, 2039) == (1500 - 2039, 0)
+
+
+@pytest.mark.parametrize("m", [2039, 2029, 2027, 1024, 511, 491, 487])
+def test_h0_reduce_is_the_centred_residue(m):
+    """Over the whole range of the GEMM sums (|t| <= 2^24): the fold result is
+    congruent to t, lies in [-floor(m/2), m - floor(m/2)), and takes at most
+    five folds (the stage kernel's fixed count for the slowest modulus)."""
+    rng = np.random.default_rng(19)
+    ts = list(range(-5000, 5001)) + [(1 << 24) - k for k in range(300)] + [-(1 << 24) + k for k in range(300)]
+    ts += [int(x) for x in rng.integers(-(1 << 24), (1 << 24) + 1, size=20000)]
+    worst = 0
+    for t in ts:
+        r, folds = A.h0_reduce(t, m)
+        assert (r - t) % m == 0 and -(m // 2) <= r < m - m // 2
+        worst = max(worst, folds)
+    assert worst <= 5
