@@ -30,7 +30,7 @@ SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters in
 # profiles/ob_stage_kernel_fp16_1024cubed_counters.md; valid only for the
 # kernel sources they were taken with (fingerprint below), else null.
-TRAFFIC_MEASURED = {"bytes": 34.58e9, "sources_sha256_16": "968add026a64bac3"}
+TRAFFIC_MEASURED = {"bytes": 34.58e9, "sources_sha256_16": "42c4e8daf1e07560"}
 KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_device.h",
                   "paper_2606_23698_amd/csrc/ob_recon.h", "paper_2606_23698_amd/csrc/obfft_internal.h"]
 
@@ -87,7 +87,8 @@ def stage_durations(plan, x, y, ws_a, reps):
 
 
 def precision_sweep(api, x, y_ref, steps):
-    """The other substrates (bit-identical outputs) and the FP32 target at the same size."""
+    """The other substrates and the H0 fold reduction (bit-identical outputs) and
+    the FP32 target at the same size."""
     import torch
     out = {}
     for sub in ("fp8", "int8"):
@@ -99,6 +100,15 @@ def precision_sweep(api, x, y_ref, steps):
         print(f"[bench] {sub}: {ms:.2f} ms, identical={same}", file=sys.stderr, flush=True)
         del y, plan
         torch.cuda.empty_cache()
+    # H0 ablation: fold-and-add reduction of the seven friendly moduli
+    plan = api.Plan(tuple(x.shape), reduction="h0")
+    y = torch.empty_like(x)
+    ms, _ = time_steps(lambda: plan.forward(x, y), steps, 1)
+    same = bool(torch.equal(torch.view_as_real(y), torch.view_as_real(y_ref)))
+    out["h0_fold_reduction"] = {"ms": round(ms, 3), "bit_identical_to_default": same}
+    print(f"[bench] h0 fold reduction: {ms:.2f} ms, identical={same}", file=sys.stderr, flush=True)
+    del y, plan
+    torch.cuda.empty_cache()
     x32 = x.to(torch.complex64)
     plan = api.Plan(tuple(x.shape), precision="fp32")
     y32 = torch.empty_like(x32)
@@ -256,6 +266,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--substrate", default="auto")
+    ap.add_argument("--reduction", default="reciprocal", choices=["reciprocal", "h0"],
+                    help="residue reduction of the stage kernels (h0: fold-and-add ablation)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=2)
     ap.add_argument("--no-native", action="store_true", help="skip the native FP64 comparator")
@@ -278,7 +290,7 @@ def main():
     dev = torch.device("cuda:0")
     N = args.size
     shape = (N, N, N)
-    plan = api.Plan(shape, substrate=args.substrate)
+    plan = api.Plan(shape, substrate=args.substrate, reduction=args.reduction)
     info = plan.info()
     x = inputs.device_uniform(shape, 2, device=dev)
     y = torch.empty_like(x)
@@ -329,7 +341,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"forward complex FP64 3-D FFT {N}x{N}x{N}, Re/Im uniform[-1,1) seed 2",
                    "n": shape, "p": info["p"], "q": info["q"], "moduli": info["r"],
-                   "substrate": SUB_NAME[info["substrate"]]},
+                   "substrate": SUB_NAME[info["substrate"]], "reduction": args.reduction},
         "native_fp64_ms": round(ms_nat, 3) if ms_nat == ms_nat else None,
         "emulated_over_native": round(ms / ms_nat, 2) if ms_nat == ms_nat else None,
         "hbm_roof_ms": round(roof_ms, 3),
@@ -343,7 +355,7 @@ def main():
         "wall_ms_per_step": round(wall, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": measured_traffic(N, info["substrate"]),
+                     "traffic": measured_traffic(N, info["substrate"]) if args.reduction == "reciprocal" else None,
                      "kernel": "ob_stage_kernel", "avg_launch_ms": round(stage_ms, 3),
                      "algorithmic_per_launch": f"{C_EPI_MIN} integer ops x {n_out_launch} outputs"},
     }

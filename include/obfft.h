@@ -79,6 +79,19 @@ enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
  *          INT8 */
 enum { OBFFT_SUB_FP8 = 0, OBFFT_SUB_INT8 = 1, OBFFT_SUB_FP16 = 2, OBFFT_SUB_AUTO = 3 };
 
+/* Residue reduction of the GEMM sums (exact integers |t| <= 2^24) in the
+ * stage kernels.
+ *   RECIPROCAL : t - m rne(t / m) in FP32, three vector instructions for any
+ *                modulus (default)
+ *   H0         : fold-and-add for the reduction-friendly moduli m = 2^b - c
+ *                with c <= 31 or c = 0 (Sec. 2; rung H0 of the co-design
+ *                ladder, Sec. 8.3: 2039, 2029, 2027, 1024, 511, 491, 487 of
+ *                the FP64 set), the reciprocal form for the rest.  An
+ *                ablation: FP16 substrate and FP64 target only, single
+ *                transforms only (else OBFFT_INVALID_VALUE); outputs are
+ *                bit-identical to RECIPROCAL (residues are unique). */
+enum { OBFFT_RED_RECIPROCAL = 0, OBFFT_RED_H0 = 1 };
+
 typedef struct {
   int precision;            /* OBFFT_PREC_* */
   int substrate;            /* OBFFT_SUB_* */
@@ -86,7 +99,8 @@ typedef struct {
   int q[3];                 /* per axis; p*q must equal the extent */
   int n_moduli_override;    /* 0 = the precision's set; else use moduli_override */
   const int32_t* moduli_override; /* host pointer, pairwise coprime, each < 2048 */
-  int reserved[8];
+  int reduction;            /* OBFFT_RED_* (0 = default) */
+  int reserved[7];
 } obfft_options_t;
 
 typedef struct {

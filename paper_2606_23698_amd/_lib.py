@@ -25,7 +25,8 @@ class PlanInfo(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("substrate", ctypes.c_int), ("p", ctypes.c_int * 3),
                 ("q", ctypes.c_int * 3), ("n_moduli_override", ctypes.c_int),
-                ("moduli_override", ctypes.POINTER(ctypes.c_int32)), ("reserved", ctypes.c_int * 8)]
+                ("moduli_override", ctypes.POINTER(ctypes.c_int32)), ("reduction", ctypes.c_int),
+                ("reserved", ctypes.c_int * 7)]
 
 
 class TapsLayout(ctypes.Structure):

@@ -13,6 +13,9 @@ from . import _lib as L
 
 SUBSTRATES = {"fp8": 0, "int8": 1, "fp16": 2, "auto": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+# residue reduction of the stage kernels: FP32 reciprocal (default) or the
+# fold-and-add form of the friendly moduli (H0 ablation)
+REDUCTIONS = {"reciprocal": 0, "h0": 1}
 
 
 def _stream(stream):
@@ -46,11 +49,12 @@ def _check_dev(t, dtype, numel=None, name="tensor"):
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
 
-def options(precision="fp64", substrate="auto", pq=None, moduli=None):
+def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal"):
     opt = L.Options()
     L.lib().obfft_options_default(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
     opt.substrate = SUBSTRATES[substrate]
+    opt.reduction = REDUCTIONS[reduction]
     if pq is not None:
         for a, (p, q) in enumerate(pq):
             opt.p[a] = int(p)
@@ -66,12 +70,12 @@ def options(precision="fp64", substrate="auto", pq=None, moduli=None):
 class Plan:
     """An Ozaki-Bailey 3-D FFT plan for one shape on the current device."""
 
-    def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None):
+    def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal"):
         self.shape = tuple(int(n) for n in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must have three extents")
         self.precision = precision
-        opt, keep = options(precision, substrate, pq, moduli)
+        opt, keep = options(precision, substrate, pq, moduli, reduction)
         h = ctypes.c_void_p()
         L.check(L.lib().obfft_plan_create(ctypes.byref(h), *self.shape, ctypes.byref(opt)),
                 "obfft_plan_create")

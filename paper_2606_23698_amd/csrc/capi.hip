@@ -13,7 +13,7 @@
 #include "plan_math.h"
 
 namespace obfft {
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipStream_t st);
+hipError_t launch_stage(int sub, int tgt, bool h0, const StageParams& P, dim3 grid, hipStream_t st);
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
@@ -46,6 +46,7 @@ struct obfft_plan_s {
   int64_t n[3] = {0, 0, 0};
   int p[3] = {0, 0, 0}, q[3] = {0, 0, 0};
   int precision = 0, substrate = SUB_FP8, kbits = 53;
+  int reduction = OBFFT_RED_RECIPROCAL;
   ModSet H;
   CrtConsts C;
   ModConsts MC;
@@ -134,6 +135,7 @@ static void build_modconsts(const ModSet& H, ModConsts& MC, int substrate) {
     MC.md[i] = (double)H.m[i];
     MC.nd[i] = fp8_digits(H.m[i]);
     MC.sub[i] = substrate;
+    h0_fold_form(H.m[i], &MC.fold_b[i], &MC.fold_c[i], &MC.fold_n[i]);
   }
 }
 
@@ -168,6 +170,10 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   if (sub == OBFFT_SUB_AUTO) sub = fp16_ok ? OBFFT_SUB_FP16 : OBFFT_SUB_INT8;
   if (sub == OBFFT_SUB_FP16 && !fp16_ok) return OBFFT_UNSUPPORTED_SIZE;
   plan->substrate = sub;
+  // the fold-and-add reduction is an ablation of the default FP64 path
+  plan->reduction = opt->reduction;
+  if (opt->reduction == OBFFT_RED_H0 && (sub != OBFFT_SUB_FP16 || plan->precision != OBFFT_PREC_FP64))
+    return OBFFT_INVALID_VALUE;
   int64_t kmax = 0;
   for (int a = 0; a < 3; a++) {
     int64_t N = plan->n[a];
@@ -258,6 +264,7 @@ extern "C" obfft_status_t obfft_plan_create(obfft_plan_t* out, int64_t n1, int64
   if (!opt) opt = &def;
   if (opt->precision != OBFFT_PREC_FP64 && opt->precision != OBFFT_PREC_FP32) return OBFFT_INVALID_VALUE;
   if (opt->substrate < 0 || opt->substrate > OBFFT_SUB_AUTO) return OBFFT_INVALID_VALUE;
+  if (opt->reduction != OBFFT_RED_RECIPROCAL && opt->reduction != OBFFT_RED_H0) return OBFFT_INVALID_VALUE;
   obfft_plan_t plan = new (std::nothrow) obfft_plan_s();
   if (!plan) return OBFFT_ALLOC_FAILED;
   plan->n[0] = n1;
@@ -460,7 +467,7 @@ static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int dire
   P.extra_shift = extra_shift;
   P.dbg_res = dbg;
   if (tiles <= 0) return OBFFT_SUCCESS;
-  if (launch_stage(plan->substrate, plan->precision, P, grid, st) != hipSuccess)
+  if (launch_stage(plan->substrate, plan->precision, plan->reduction == OBFFT_RED_H0, P, grid, st) != hipSuccess)
     return OBFFT_HIP_ERROR;
   return OBFFT_SUCCESS;
 }
@@ -682,7 +689,7 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
   obfft_options_t def;
   obfft_options_default(&def);
   if (!opt) opt = &def;
-  if (opt->precision != OBFFT_PREC_FP64) return OBFFT_INVALID_VALUE;
+  if (opt->precision != OBFFT_PREC_FP64 || opt->reduction != OBFFT_RED_RECIPROCAL) return OBFFT_INVALID_VALUE;
   obfft_plan_t bp = new (std::nothrow) obfft_plan_s();
   if (!bp) return OBFFT_ALLOC_FAILED;
   bp->batch_count = count;

@@ -36,6 +36,21 @@ __device__ __forceinline__ float canonical_f32(float x, float m, float inv_m) {
   return r < 0.0f ? r + m : r;
 }
 
+// A centred residue of an exact FP32 integer (|x| <= 2^24) by the
+// fold-and-add reduction of a friendly modulus m = 2^b - c (Sec. 2; rung H0
+// of the co-design ladder, Sec. 8.3).  Since 2^b = c (mod m), t = 2^b h + l
+// (h = t >> b arithmetic, l = t mod 2^b) is congruent to c h + l.  nf folds
+// leave t in [-c, 2^b - 1 + c]; one conditional subtraction then gives
+// [-floor(m/2), m - floor(m/2)).  m = 2^b (c = 0): the low b bits,
+// sign-extended.
+__device__ __forceinline__ float fold_reduce_f32(float x, int m, int b, int c, int nf) {
+  int t = (int)x;
+  if (c == 0) return (float)((t << (32 - b)) >> (32 - b));
+  const int mask = (1 << b) - 1;
+  for (int f = 0; f < nf; f++) t = __mul24(c, t >> b) + (t & mask);  // |t >> b| < 2^23: one v_mad_i32_i24
+  return (float)(t >= m - (m >> 1) ? t - m : t);
+}
+
 // ---- MFMA wrappers ----
 __device__ __forceinline__ v4f mfma_fp8(long a, long b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);

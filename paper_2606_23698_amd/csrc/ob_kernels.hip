@@ -254,7 +254,9 @@ __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int6
   }
 }
 
-template <int SUB, int TGT, int KMAX, bool FULL = false>
+// H0: the residue reduction after the GEMM takes the fold-and-add form for
+// the friendly moduli (FP16 substrate; the reciprocal form otherwise).
+template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, int64_t g) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
@@ -372,9 +374,20 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     // (Alg. 1 combines; the Phase-A carrier takes them signed, |v| <= m/2 + 2.
     // Rows past K hold zero products and are never stored.)
     float rrv[4], riv[4];
+    int fm = 0, fb = 0, fc = 0, fn = 0;
+    if (H0) {
+      const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)P.mc;
+      fm = MC.m[i];
+      fb = MC.fold_b[i];
+      fc = MC.fold_c[i];
+      fn = MC.fold_n[i];
+    }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      if (SUB != SUB_FP8) {
+      if (SUB == SUB_FP16 && H0 && fb != 0) {
+        rrv[v] = fold_reduce_f32(Dv[v], fm, fb, fc, fn);
+        riv[v] = fold_reduce_f32(Fv[v], fm, fb, fc, fn);
+      } else if (SUB != SUB_FP8) {
         rrv[v] = reduce_f32(Dv[v], mf, imf);
         riv[v] = reduce_f32(Fv[v], mf, imf);
       } else {
@@ -626,12 +639,12 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   }
 }
 
-template <int SUB, int TGT, int KMAX, bool FULL>
+template <int SUB, int TGT, int KMAX, bool FULL, bool H0>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_stage_kernel(
     const StageParams P) {
   int64_t c, g;
   grid_tile(P, c, g);
-  stage_tile<SUB, TGT, KMAX, FULL>(P, c, g);
+  stage_tile<SUB, TGT, KMAX, FULL, H0>(P, c, g);
 }
 
 // Batched stage: one workgroup per tile of the members of one Bailey pass
@@ -663,51 +676,57 @@ __global__ void digits_to_fp8_kernel(uint8_t* p, int64_t n4) {
 }
 
 // ---- host-side launch helpers ----
-template <int SUB, int TGT, int KMAX, bool FULL>
+template <int SUB, int TGT, int KMAX, bool FULL, bool H0>
 static hipError_t launch_stage_t(const StageParams& P, dim3 grid, hipStream_t st) {
   int lds = StageLds<SUB, TGT, KMAX>::bytes(P.K);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX, FULL>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX, FULL, H0>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL>), grid, dim3(kThreads), lds, st, P);
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL, H0>), grid, dim3(kThreads), lds, st, P);
   return hipGetLastError();
 }
 
-// Full-length variants for the default substrate at K = 16 and 32 (the
-// power-of-two splits); everything else takes the general kernel.
-template <int SUB, int TGT>
+// Full-length variants for the default substrate at K = 8, 12, 16 and 32;
+// everything else takes the general kernel.
+template <int SUB, int TGT, bool H0>
 static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st) {
+  constexpr bool F = SUB == SUB_FP16;
   int K = P.K;
-  if (K <= 4) return launch_stage_t<SUB, TGT, 4, false>(P, grid, st);
+  if (K <= 4) return launch_stage_t<SUB, TGT, 4, false, H0>(P, grid, st);
   if (K <= 8) {
-    if (SUB == SUB_FP16 && K == 8) return launch_stage_t<SUB, TGT, 8, SUB == SUB_FP16>(P, grid, st);
-    return launch_stage_t<SUB, TGT, 8, false>(P, grid, st);
+    if (F && K == 8) return launch_stage_t<SUB, TGT, 8, F, H0>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 8, false, H0>(P, grid, st);
   }
   if (K <= 12) {
-    if (SUB == SUB_FP16 && K == 12) return launch_stage_t<SUB, TGT, 12, SUB == SUB_FP16>(P, grid, st);
-    return launch_stage_t<SUB, TGT, 12, false>(P, grid, st);
+    if (F && K == 12) return launch_stage_t<SUB, TGT, 12, F, H0>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 12, false, H0>(P, grid, st);
   }
   if (K <= 16) {
-    if (SUB == SUB_FP16 && K == 16) return launch_stage_t<SUB, TGT, 16, SUB == SUB_FP16>(P, grid, st);
-    return launch_stage_t<SUB, TGT, 16, false>(P, grid, st);
+    if (F && K == 16) return launch_stage_t<SUB, TGT, 16, F, H0>(P, grid, st);
+    return launch_stage_t<SUB, TGT, 16, false, H0>(P, grid, st);
   }
-  if (SUB == SUB_FP16 && K == 32) return launch_stage_t<SUB, TGT, 32, SUB == SUB_FP16>(P, grid, st);
-  return launch_stage_t<SUB, TGT, 32, false>(P, grid, st);
+  if (F && K == 32) return launch_stage_t<SUB, TGT, 32, F, H0>(P, grid, st);
+  return launch_stage_t<SUB, TGT, 32, false, H0>(P, grid, st);
 }
 
-hipError_t launch_stage(int sub, int tgt, const StageParams& P, dim3 grid, hipStream_t st) {
-  if (sub == SUB_FP16)
-    return tgt == 0 ? launch_stage_k<SUB_FP16, 0>(P, grid, st)
-                    : launch_stage_k<SUB_FP16, 1>(P, grid, st);
+// h0: the fold-and-add reduction of the friendly moduli (FP16 substrate,
+// FP64 target only; the plan checks it).
+hipError_t launch_stage(int sub, int tgt, bool h0, const StageParams& P, dim3 grid, hipStream_t st) {
+  if (sub == SUB_FP16) {
+    if (h0) return tgt == 0 ? launch_stage_k<SUB_FP16, 0, true>(P, grid, st) : hipErrorInvalidValue;
+    return tgt == 0 ? launch_stage_k<SUB_FP16, 0, false>(P, grid, st)
+                    : launch_stage_k<SUB_FP16, 1, false>(P, grid, st);
+  }
+  if (h0) return hipErrorInvalidValue;
   if (sub == SUB_INT8)
-    return tgt == 0 ? launch_stage_k<SUB_INT8, 0>(P, grid, st)
-                    : launch_stage_k<SUB_INT8, 1>(P, grid, st);
-  return tgt == 0 ? launch_stage_k<SUB_FP8, 0>(P, grid, st)
-                  : launch_stage_k<SUB_FP8, 1>(P, grid, st);
+    return tgt == 0 ? launch_stage_k<SUB_INT8, 0, false>(P, grid, st)
+                    : launch_stage_k<SUB_INT8, 1, false>(P, grid, st);
+  return tgt == 0 ? launch_stage_k<SUB_FP8, 0, false>(P, grid, st)
+                  : launch_stage_k<SUB_FP8, 1, false>(P, grid, st);
 }
 
 template <int SUB, int KMAX, bool FULL>

@@ -69,7 +69,18 @@ struct ModConsts {
   double md[kMaxModuli];
   int nd[kMaxModuli];    // digits per residue on the FP8 substrate (2 or 3)
   int sub[kMaxModuli];   // substrate of each modulus
+  // Fold-and-add form of a reduction-friendly modulus m = 2^b - c (Sec. 2,
+  // Sec. 8.3 rung H0: a power of two, or a small complement
+  // c <= kH0MaxComplement): fold_n
+  // folds t <- c (t >> b) + (t mod 2^b) take any |t| <= 2^24 into
+  // [-c, 2^b - 1 + c].  fold_b = 0 marks a modulus that keeps the reciprocal
+  // reduction.  Used only by plans that ask for the fold (OBFFT_RED_H0).
+  int fold_b[kMaxModuli], fold_c[kMaxModuli], fold_n[kMaxModuli];
 };
+
+// Largest complement 2^b - m of a modulus reduced by folds.  The seven
+// friendly members of the FP64 set have c <= 25; the next one, 961, has 63.
+constexpr int kH0MaxComplement = 31;
 
 // One Bailey stage of one axis, as launched.
 struct StageParams {

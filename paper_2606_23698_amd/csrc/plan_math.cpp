@@ -429,6 +429,31 @@ bool fp16_single_slot_ok(int m) {
   return 2LL * kMaxK * h * (h + e) <= (1LL << 24);
 }
 
+static int64_t floor_div(int64_t a, int64_t d) { return a >= 0 ? a / d : -((-a + d - 1) / d); }
+
+void h0_fold_form(int m, int* b, int* c, int* nf) {
+  int bb = 0;
+  while ((1 << bb) < m) bb++;
+  const int cc = (1 << bb) - m;
+  *b = 0;
+  *c = cc;
+  *nf = 0;
+  if (m < 2 || cc > kH0MaxComplement) return;
+  // interval of t after each fold: t' = c h + l, h in [floor(lo / 2^b),
+  // floor(hi / 2^b)], l in [0, 2^b)
+  int64_t lo = -(1LL << 24), hi = 1LL << 24;
+  const int64_t B = 1LL << bb;
+  int n = 0;
+  while (cc > 0 && (lo < -cc || hi > B - 1 + cc)) {
+    const int64_t hl = floor_div(lo, B), hh = floor_div(hi, B);
+    lo = cc * hl;
+    hi = cc * hh + B - 1;
+    if (++n > 32) return;  // no convergence: keep the reciprocal reduction
+  }
+  *b = bb;
+  *nf = n;
+}
+
 void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
                           int64_t p, int64_t q, int stage, int direction, int substrate,
                           int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L) {

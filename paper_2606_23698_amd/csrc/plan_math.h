@@ -42,6 +42,11 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
 // True when residues mod m may enter the FP16 residue GEMM as one slot per
 // index (no limb split) with an exact FP32 accumulation.
 bool fp16_single_slot_ok(int m);
+// Fold-and-add form of m for the H0 reduction of exact sums |t| <= 2^24:
+// m = 2^b - c and the number of folds that take every such t into
+// [-c, 2^b - 1 + c] (nf = 0 for a power of two).  *b = 0 when m is not
+// friendly (complement above kH0MaxComplement).
+void h0_fold_form(int m, int* b, int* c, int* nf);
 void build_phaseA_operand(const ModSet& H, std::vector<uint16_t>& out, int* npairs);
 
 }  // namespace obfft

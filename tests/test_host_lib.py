@@ -74,6 +74,25 @@ def test_unsupported_and_invalid_sizes():
     assert e.value.status == 1
 
 
+def test_h0_reduction_option_is_validated():
+    """The fold-and-add reduction is an FP16-substrate, FP64-target ablation of
+    single transforms; anything else is rejected before any device work."""
+    import ctypes
+    from paper_2606_23698_amd import api, _lib
+    from paper_2606_23698_amd._lib import ObfftError
+    for kw in ({"substrate": "int8"}, {"substrate": "fp8"}, {"precision": "fp32"}):
+        with pytest.raises(ObfftError) as e:
+            api.Plan((32, 32, 32), reduction="h0", **kw)
+        assert e.value.status == 1, kw
+    opt, _ = api.options()
+    opt.reduction = 2
+    h = ctypes.c_void_p()
+    assert _lib.lib().obfft_plan_create(ctypes.byref(h), 32, 32, 32, ctypes.byref(opt)) == 1
+    opt.reduction = 1
+    shapes = (ctypes.c_int64 * 3)(32, 32, 32)
+    assert _lib.lib().obfft_batch_plan_create(ctypes.byref(h), 1, shapes, ctypes.byref(opt)) == 1
+
+
 def test_fp16_substrate_rejects_a_large_modulus_past_the_split():
     """FP16 takes one slot per index for moduli 4.. of an FP64 set, which is
     exact only when 64 h (h + e) <= 2^24 (h = floor(m/2); e = 0 for a power
