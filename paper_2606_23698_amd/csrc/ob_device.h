@@ -45,7 +45,7 @@ __device__ __forceinline__ float canonical_f32(float x, float m, float inv_m) {
 // sign-extended.
 __device__ __forceinline__ float fold_reduce_f32(float x, int m, int b, int c, int nf) {
   int t = (int)x;
-  if (c == 0) return (float)((t << (32 - b)) >> (32 - b));
+  if (c == 0) return (float)((int)((uint32_t)t << (32 - b)) >> (32 - b));
   const int mask = (1 << b) - 1;
   for (int f = 0; f < nf; f++) t = __mul24(c, t >> b) + (t & mask);  // |t >> b| < 2^23: one v_mad_i32_i24
   return (float)(t >= m - (m >> 1) ? t - m : t);

@@ -5,7 +5,9 @@
   and emulated error no worse than the native FP64 FFT's (both against the
   double-double DFT on sampled lines).
 * 1024^3 uniform[-1, 1): sampled output lines bit-exact against the oracle's
-  exact pipeline (the oracle evaluates only the cost cone of each line).
+  exact pipeline (the oracle evaluates only the cost cone of each line), for
+  the FP64 and the FP32 target; the INT8, FP8 and H0 variants equal the
+  default over the whole array.
 * the differentiable spectral loss: adjoint gradient against central finite
   differences at 16^3 and against a native-FP64 reference gradient at 512^3.
 """
@@ -94,6 +96,52 @@ def test_1024cubed_sampled_lines_bit_exact(gpu):
             a2 = ox.lines_at(a3, N, p2, q2, k2)                              # [j1]
             a1 = ox.lines(a2.reshape(1, N), N, p1, q1)[0]
             assert np.count_nonzero(got[(k2, k3)] != a1) == 0, (k2, k3)
+
+
+def test_1024cubed_fp32_target_sampled_lines_bit_exact(gpu):
+    """The FP32-target variant (r = 6, k = 24, complex64) at 1024^3: six
+    final-axis output lines against the oracle's exact pipeline at that
+    precision (cost cones as in the FP64 test)."""
+    from paper_2606_23698_amd import api
+    N = 1024
+    shape = (N, N, N)
+    plan = api.Plan(shape, precision="fp32")
+    (p1, q1), (p2, q2), (p3, q3) = _pq(plan)
+    xt = inputs.device_uniform(shape, 2, device=gpu).to(torch.complex64)
+    torch.cuda.empty_cache()
+    y = plan.forward(xt)
+    torch.cuda.synchronize()
+    samples = [(0, 7), (333, 7), (1023, 7), (5, 600), (512, 600), (1000, 600)]
+    got = {s: y[:, s[0], s[1]].cpu().numpy() for s in samples}
+    del y
+    x = xt.cpu().numpy()
+    del xt
+    torch.cuda.empty_cache()
+    for k3 in sorted({k3 for _, k3 in samples}):
+        a3 = ox.lines_at(x.reshape(-1, N), N, p3, q3, k3, precision=1).reshape(N, N)
+        for k2 in sorted({k2 for k2, kk in samples if kk == k3}):
+            a2 = ox.lines_at(a3, N, p2, q2, k2, precision=1)
+            a1 = ox.lines(a2.reshape(1, N), N, p1, q1, precision=1)[0]
+            assert got[(k2, k3)].dtype == np.complex64
+            assert np.count_nonzero(got[(k2, k3)] != a1) == 0, (k2, k3)
+
+
+def test_1024cubed_substrates_bit_identical(gpu):
+    """At the full 1024^3 size the INT8 and FP8 residue GEMMs (and the H0
+    reduction) give the default FP16 path's output bit for bit over the whole
+    array: residues of an exact integer product are unique."""
+    from paper_2606_23698_amd import api
+    N = 1024
+    shape = (N, N, N)
+    xt = inputs.device_uniform(shape, 2, device=gpu)
+    ref = api.Plan(shape).forward(xt)
+    for kw in ({"substrate": "int8"}, {"substrate": "fp8"}, {"reduction": "h0"}):
+        plan = api.Plan(shape, **kw)
+        y = plan.forward(xt)
+        torch.cuda.synchronize()
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref)), kw
+        del y, plan
+        torch.cuda.empty_cache()
 
 
 def test_spectral_loss_gradient_finite_differences(gpu):
