@@ -22,7 +22,7 @@ hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* r
 hipError_t launch_digits_to_fp8(uint8_t* p, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int kind, const void* a, const void* b, void* d, hipStream_t st);
 hipError_t launch_scale(void* data, int64_t n_scalars, double factor, int tgt, hipStream_t st);
-int stage_cols_per_wg(int K);
+int stage_cols_per_wg(int K, int sub);
 hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, const int64_t* first,
                         const uint16_t* tmember, int64_t total, hipStream_t st);
 int kclass_of(int K);
@@ -191,7 +191,7 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
     // holds fewer than kMaxTiles workgroups
     const int64_t n_all = plan->n[0] * plan->n[1] * plan->n[2];
     if (n_all / qq >= ((int64_t)1 << 31)) return OBFFT_UNSUPPORTED_SIZE;
-    const int64_t c1 = stage_cols_per_wg(qq), c2 = stage_cols_per_wg(pp);
+    const int64_t c1 = stage_cols_per_wg(qq, sub), c2 = stage_cols_per_wg(pp, sub);
     if ((n_all / qq + c1 - 1) / c1 >= kMaxTiles || qq * ((n_all / N + c2 - 1) / c2) >= kMaxTiles)
       return OBFFT_UNSUPPORTED_SIZE;
   }
@@ -440,7 +440,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     P.s_in_s = p * inner;
     P.s_out_g = inner;
     P.s_out_t = p * inner;
-    int ncw = stage_cols_per_wg(P.K);
+    int ncw = stage_cols_per_wg(P.K, plan->substrate);
     grid = (P.ncols + ncw - 1) / ncw;
   } else {
     P.K = (int)p;
@@ -450,7 +450,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     P.s_in_s = inner;
     P.s_out_g = inner;
     P.s_out_t = q * inner;
-    int ncw = stage_cols_per_wg(P.K);
+    int ncw = stage_cols_per_wg(P.K, plan->substrate);
     P.tiles_per_g = (int)((P.ncols + ncw - 1) / ncw);
     P.g_minor = inner == 1;
     P.gblock = (q % kGroupBlock) == 0 ? kGroupBlock : (int)q;
