@@ -3,6 +3,8 @@
 Every member's output must be bit-identical to the single-transform path
 (the same plan, factorisation and axis order), on several graph replays with
 eager work and synchronisation in between, and with the graph switched off.
+At the full 64-transform workload, the smallest members are also checked
+against the oracle's exact pipeline.
 """
 import numpy as np
 import pytest
@@ -46,3 +48,24 @@ def test_batch_on_the_two_m_tile_shape(gpu):
     torch.cuda.synchronize()
     for o, r, s in zip(outs, ref, shapes):
         assert torch.equal(o, r), s
+
+
+def test_batch_64_uneven_workload(gpu):
+    """The full 64-transform workload (extents from {64, 96, 128, 192, 256} per
+    axis, seed 3): every member equals its single-transform output bit for bit,
+    and the three smallest members equal the oracle's exact pipeline."""
+    from oracle import exact as ox
+    from paper_2606_23698_amd import api
+    shapes, _ = inputs.batch_shapes(3, 64)
+    xs = [inputs.device_uniform(s, 3 + i, device=gpu) for i, s in enumerate(shapes)]
+    bp = api.BatchPlan(shapes)
+    outs = bp.forward(xs)
+    torch.cuda.synchronize()
+    for i, (s, x, o) in enumerate(zip(shapes, xs, outs)):
+        assert torch.equal(o, api.get_plan(s).forward(x)), (i, s)
+    smallest = sorted(range(len(shapes)), key=lambda i: int(np.prod(shapes[i])))[:3]
+    for i in smallest:
+        plan = api.get_plan(shapes[i])
+        pq = tuple(zip(plan.info()["p"], plan.info()["q"]))
+        ref = ox.fft3_exact(xs[i].cpu().numpy(), pq)
+        assert np.count_nonzero(outs[i].cpu().numpy() != ref) == 0, (i, shapes[i])
