@@ -72,6 +72,10 @@ def test_unsupported_and_invalid_sizes():
     with pytest.raises(ObfftError) as e:
         api.Plan((32, 32, 32), moduli=[2039, 2039, 1024])      # not coprime
     assert e.value.status == 1
+    # 4096 has no split p x q with both factors at most 32 (the longest contraction)
+    with pytest.raises(ObfftError) as e:
+        api.Plan((4096, 4096, 4096))
+    assert e.value.status == 2
 
 
 def test_h0_reduction_option_is_validated():
