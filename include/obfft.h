@@ -100,7 +100,13 @@ typedef struct {
   int n_moduli_override;    /* 0 = the precision's set; else use moduli_override */
   const int32_t* moduli_override; /* host pointer, pairwise coprime, each < 2048 */
   int reduction;            /* OBFFT_RED_* (0 = default) */
-  int reserved[7];
+  int group_block;          /* tile order of stage 2 on the contiguous axis: the number of
+                               twiddle groups k2 whose tiles of one column block run back to
+                               back on one XCD, so that their partial output lines merge in
+                               its L2.  0 = library default (8 when it divides q); else one of
+                               1, 2, 4, 8, 16, 32 (else OBFFT_INVALID_VALUE), used where it
+                               divides q of that axis.  Changes speed only, never results. */
+  int reserved[6];
 } obfft_options_t;
 
 typedef struct {

@@ -26,7 +26,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("substrate", ctypes.c_int), ("p", ctypes.c_int * 3),
                 ("q", ctypes.c_int * 3), ("n_moduli_override", ctypes.c_int),
                 ("moduli_override", ctypes.POINTER(ctypes.c_int32)), ("reduction", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("group_block", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
 
 class TapsLayout(ctypes.Structure):

@@ -49,12 +49,13 @@ def _check_dev(t, dtype, numel=None, name="tensor"):
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
 
-def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal"):
+def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal", group_block=0):
     opt = L.Options()
     L.lib().obfft_options_default(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
     opt.substrate = SUBSTRATES[substrate]
     opt.reduction = REDUCTIONS[reduction]
+    opt.group_block = int(group_block)
     if pq is not None:
         for a, (p, q) in enumerate(pq):
             opt.p[a] = int(p)
@@ -70,12 +71,13 @@ def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction=
 class Plan:
     """An Ozaki-Bailey 3-D FFT plan for one shape on the current device."""
 
-    def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal"):
+    def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal",
+                 group_block=0):
         self.shape = tuple(int(n) for n in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must have three extents")
         self.precision = precision
-        opt, keep = options(precision, substrate, pq, moduli, reduction)
+        opt, keep = options(precision, substrate, pq, moduli, reduction, group_block)
         h = ctypes.c_void_p()
         L.check(L.lib().obfft_plan_create(ctypes.byref(h), *self.shape, ctypes.byref(opt)),
                 "obfft_plan_create")

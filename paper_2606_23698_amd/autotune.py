@@ -1,10 +1,13 @@
-"""Autotuner: per shape, the six-step factorisation and the MFMA substrate.
+"""Autotuner: per shape, the six-step factorisation, the MFMA substrate and
+the tile order of the contiguous axis's second stage.
 
 Candidates per axis are the admissible splits N = p q (both <= 32;
 p <= q and p > q are different plans with different output bits, as the
 factorisation fixes which roundings happen where); candidates for the
 substrate are FP16, INT8 and FP8 (bit-identical outputs for one
-factorisation).  Every candidate plan is
+factorisation); candidates for the tile order are the group blocks 4, 8,
+16 and 32 that divide q of the contiguous axis (how many twiddle groups
+run back to back on one XCD; results never depend on it).  Every candidate plan is
 timed on the device with HIP events (median of `reps` forward transforms on
 a seeded input) and the fastest is cached in a JSON file keyed by shape,
 precision and device name ($OBFFT_AUTOTUNE_CACHE, default
@@ -70,10 +73,10 @@ def _time_plan(plan, x, reps):
     return ts[len(ts) // 2]
 
 
-def _try_time(shape, precision, sub, pq, x, reps):
+def _try_time(shape, precision, sub, pq, x, reps, group_block=0):
     from ._lib import ObfftError
     try:
-        plan = api.Plan(shape, precision=precision, substrate=sub, pq=pq)
+        plan = api.Plan(shape, precision=precision, substrate=sub, pq=pq, group_block=group_block)
     except ObfftError:
         return None  # e.g. FP16 with a modulus set it cannot host
     try:
@@ -84,11 +87,11 @@ def _try_time(shape, precision, sub, pq, x, reps):
 
 def tune(shape, precision="fp64", substrates=("fp16", "int8", "fp8"), reps=3, max_splits=2,
          use_cache=True):
-    """Returns {"substrate", "pq", "ms"} for the fastest candidate plan of `shape`.
+    """Returns {"substrate", "pq", "group_block", "ms"} for the fastest candidate plan of `shape`.
 
     Phase 1 times every combination of the `max_splits` most balanced splits
     per axis on the first substrate; phase 2 times the other substrates on the
-    winning factorisation.
+    winning factorisation; phase 3 the group blocks of the winner.
     """
     shape = tuple(int(n) for n in shape)
     dev = torch.cuda.get_device_name(0)
@@ -119,6 +122,14 @@ def tune(shape, precision="fp64", substrates=("fp16", "int8", "fp8"), reps=3, ma
         ms = _try_time(shape, precision, sub, pq, x, reps)
         if ms is not None and ms < best["ms"]:
             best = {"substrate": sub, "pq": [list(v) for v in pq], "ms": ms}
+    best["group_block"] = 0
+    q3 = pq[2][1]
+    for gb in (4, 8, 16, 32):
+        if q3 % gb or gb == 8:  # 8 is the default order just timed
+            continue
+        ms = _try_time(shape, precision, best["substrate"], pq, x, reps, gb)
+        if ms is not None and ms < best["ms"]:
+            best = dict(best, group_block=gb, ms=ms)
     if use_cache:
         cache = _load()
         cache[key] = best
@@ -128,4 +139,5 @@ def tune(shape, precision="fp64", substrates=("fp16", "int8", "fp8"), reps=3, ma
 
 def tuned_plan(shape, precision="fp64", **kw):
     t = tune(shape, precision, **kw)
-    return api.Plan(shape, precision=precision, substrate=t["substrate"], pq=[tuple(v) for v in t["pq"]])
+    return api.Plan(shape, precision=precision, substrate=t["substrate"], pq=[tuple(v) for v in t["pq"]],
+                    group_block=t.get("group_block", 0))

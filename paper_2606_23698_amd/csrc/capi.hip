@@ -47,6 +47,7 @@ struct obfft_plan_s {
   int p[3] = {0, 0, 0}, q[3] = {0, 0, 0};
   int precision = 0, substrate = SUB_FP8, kbits = 53;
   int reduction = OBFFT_RED_RECIPROCAL;
+  int group_block = 0;  // 0: the library's choice
   ModSet H;
   CrtConsts C;
   ModConsts MC;
@@ -172,6 +173,7 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   plan->substrate = sub;
   // the fold-and-add reduction is an ablation of the default FP64 path
   plan->reduction = opt->reduction;
+  plan->group_block = opt->group_block;
   if (opt->reduction == OBFFT_RED_H0 && (sub != OBFFT_SUB_FP16 || plan->precision != OBFFT_PREC_FP64))
     return OBFFT_INVALID_VALUE;
   int64_t kmax = 0;
@@ -265,6 +267,8 @@ extern "C" obfft_status_t obfft_plan_create(obfft_plan_t* out, int64_t n1, int64
   if (opt->precision != OBFFT_PREC_FP64 && opt->precision != OBFFT_PREC_FP32) return OBFFT_INVALID_VALUE;
   if (opt->substrate < 0 || opt->substrate > OBFFT_SUB_AUTO) return OBFFT_INVALID_VALUE;
   if (opt->reduction != OBFFT_RED_RECIPROCAL && opt->reduction != OBFFT_RED_H0) return OBFFT_INVALID_VALUE;
+  if (opt->group_block < 0 || opt->group_block > 32 || (opt->group_block & (opt->group_block - 1)))
+    return OBFFT_INVALID_VALUE;
   obfft_plan_t plan = new (std::nothrow) obfft_plan_s();
   if (!plan) return OBFFT_ALLOC_FAILED;
   plan->n[0] = n1;
@@ -453,7 +457,8 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     int ncw = stage_cols_per_wg(P.K, plan->substrate);
     P.tiles_per_g = (int)((P.ncols + ncw - 1) / ncw);
     P.g_minor = inner == 1;
-    P.gblock = (q % kGroupBlock) == 0 ? kGroupBlock : (int)q;
+    const int gb = plan->group_block > 0 && q % plan->group_block == 0 ? plan->group_block : kGroupBlock;
+    P.gblock = (q % gb) == 0 ? gb : (int)q;
     grid = (int64_t)P.tiles_per_g * q;
   }
 }

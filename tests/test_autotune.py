@@ -28,6 +28,7 @@ def test_tuned_plan_is_bit_exact(gpu, tmp_path):
     shape = (16, 96, 64)
     best = autotune.tune(shape, reps=1)
     assert best["substrate"] in ("fp16", "int8", "fp8")
+    assert best["group_block"] in (0, 4, 16, 32)
     again = autotune.tune(shape, reps=1)          # served from the cache
     assert again == best
     plan = autotune.tuned_plan(shape, reps=1)
@@ -36,3 +37,19 @@ def test_tuned_plan_is_bit_exact(gpu, tmp_path):
     pq = tuple(tuple(v) for v in best["pq"])
     ref = ox.fft3_exact(x, pq)
     assert np.count_nonzero(y != ref) == 0
+
+
+@pytest.mark.gpu
+def test_group_block_changes_no_bits(gpu):
+    """The stage-2 tile order of the contiguous axis is a speed knob only."""
+    import torch
+    from paper_2606_23698_amd import api
+    # contiguous axis 512 = 16 x 32 (q = 32); 384 and 512 columns per group give
+    # 6 and 8 tiles per group, the two grid shapes of the group-block order
+    for shape in ((16, 24, 512), (32, 16, 512)):
+        x = torch.from_numpy(inputs.uniform(shape, 22)).to(gpu)
+        ref = api.Plan(shape).forward(x)
+        for gb in (1, 2, 4, 16, 32):
+            y = api.Plan(shape, group_block=gb).forward(x)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref)), (shape, gb)

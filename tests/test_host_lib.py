@@ -97,6 +97,15 @@ def test_h0_reduction_option_is_validated():
     assert _lib.lib().obfft_batch_plan_create(ctypes.byref(h), 1, shapes, ctypes.byref(opt)) == 1
 
 
+def test_group_block_option_is_validated():
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import ObfftError
+    for gb in (-1, 3, 12, 64):
+        with pytest.raises(ObfftError) as e:
+            api.Plan((32, 32, 32), group_block=gb)
+        assert e.value.status == 1, gb
+
+
 def test_fp16_substrate_rejects_a_large_modulus_past_the_split():
     """FP16 takes one slot per index for moduli 4.. of an FP64 set, which is
     exact only when 64 h (h + e) <= 2^24 (h = floor(m/2); e = 0 for a power
