@@ -350,6 +350,14 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     ar[u] = __builtin_rint(__builtin_ldexp(ar[u], TT::PREC - 1 - e));
     br[u] = __builtin_rint(__builtin_ldexp(br[u], TT::PREC - 1 - e));
   }
+  // FP32 target: the quantised data are integers below 2^24, exact in FP32, so
+  // their residues come from the FP32 reduction (|r| <= m/2 + 2 as in FP64)
+  float arf[KQ], brf[KQ];
+#pragma unroll
+  for (int u = 0; u < KQ; u++) {
+    arf[u] = (float)ar[u];
+    brf[u] = (float)br[u];
+  }
 
   const int mt = (MT == 2) ? (wave & 1) : 0;
   const int nt = (MT == 2) ? (wave >> 1) : wave;
@@ -474,8 +482,13 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
       int s = part * KQ + u;
       if (s < K) {
         if (SUB == SUB_FP16) {
-          ra16[u] = residue_f64(ar[u], md, imd);
-          rb16[u] = residue_f64(br[u], md, imd);
+          if (TGT == 1) {
+            ra16[u] = reduce_f32(arf[u], mf, imf);
+            rb16[u] = reduce_f32(brf[u], mf, imf);
+          } else {
+            ra16[u] = residue_f64(ar[u], md, imd);
+            rb16[u] = residue_f64(br[u], md, imd);
+          }
           if (split16) {
             la[u] = f16_limbs(ra16[u]);
             lb[u] = f16_limbs(rb16[u]);
