@@ -256,11 +256,11 @@ __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int6
 
 // H0: the residue reduction after the GEMM takes the fold-and-add form for
 // the friendly moduli (FP16 substrate; the reciprocal form otherwise).
-// PK: two columns of a 4 < K <= 8 stage per 16-row tile (fp16_packed): the
-// tile runs as a full K = 16 contraction over block-diagonal planes; thread
-// part p of a column loads half p / 2 and lane half l / 32 of the epilogue
-// reconstructs it.
-template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false, bool PK = false>
+// NP > 1: NP columns of a K <= 16 / NP stage per 16-row tile (fp16_pack): the
+// tile runs as a full K = 16 contraction over block-diagonal planes with
+// blocks of BR = 16 / NP rows; decon thread part p loads column p / (4 / NP)
+// of its group and lanes 16 BR/4 b .. of the epilogue reconstruct column b.
+template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false, int NP = 1>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, int64_t g) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
@@ -272,11 +272,13 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   constexpr int DIG = LY::DIG;
   typedef Epilogue<TT::S, TT::TZ, TT::NW> EP;
 
-  static_assert(!PK || (SUB == SUB_FP16 && KMAX == 2 * kPackRows && FULL && SH::TPC == 4),
+  constexpr bool PK = NP > 1;
+  constexpr int BR = 16 / NP;                // rows and contraction slots per packed column
+  static_assert(NP == 1 || ((NP == 2 || NP == 4) && SUB == SUB_FP16 && KMAX == 16 && FULL && SH::TPC == 4),
                 "packed columns: FP16, full 16-row tile, four parts per column");
-  constexpr int NCR = PK ? 2 * NCOL : NCOL;  // columns of the stage per tile
+  constexpr int NCR = NP * NCOL;             // columns of the stage per tile
   const int K = FULL ? KMAX : P.K;           // contraction length of the tile
-  const int KR = PK ? P.K : K;               // of one column (PK: <= kPackRows)
+  const int KR = PK ? P.K : K;               // of one column (packed: <= BR)
   int64_t* col_in = (int64_t*)(smem + 2 * DIG);
   int64_t* col_out = col_in + NCR;
   int* cexp = (int*)(col_out + NCR);
@@ -318,14 +320,14 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
   const int jc = tid % NCOL, part = tid / NCOL;
-  const int half = PK ? part >> 1 : 0;        // PK: which column of the pair
-  const int rc = PK ? 2 * jc + half : jc;     // this thread's column in the tables
+  const int blk = PK ? part / (TPC / NP) : 0;  // packed: which column of the group
+  const int rc = NP * jc + blk;                // this thread's column in the tables
   const int64_t cin = col_in[rc];
   double ar[KQ], br[KQ];
   int lmax = INT_MIN;
 #pragma unroll
   for (int u = 0; u < KQ; u++) {
-    const int s = part * KQ + u - half * kPackRows;  // index within the column
+    const int s = part * KQ + u - blk * BR;  // index within the column
     double xr = 0.0, xi = 0.0;
     if (cin >= 0 && s < KR) {
       const typename TT::V2 v = ((const OB_GLOBAL typename TT::V2*)P.in)[cin + (int64_t)s * P.s_in_s];
@@ -342,9 +344,9 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   int e = INT_MIN;
 #pragma unroll
   for (int t = 0; t < TPC; t++)
-    if (!PK || (t >> 1) == half) e = max(e, pexp[t * NCOL + jc]);
+    if (!PK || t / (TPC / NP) == blk) e = max(e, pexp[t * NCOL + jc]);
   if (e == INT_MIN) e = 0;  // all-zero column: every output is zero
-  if (PK ? (part & 1) == 0 : part == 0) cexp[rc] = e;
+  if (PK ? part % (TPC / NP) == 0 : part == 0) cexp[rc] = e;
 #pragma unroll
   for (int u = 0; u < KQ; u++) {
     ar[u] = __builtin_rint(__builtin_ldexp(ar[u], TT::PREC - 1 - e));
@@ -424,10 +426,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
       }
     }
     if (P.dbg_res) {  // canonical residue tap (tests only)
-      const int64_t co = col_out[PK ? 2 * col + (lane >> 5) : col];
+      const int eb = PK ? 4 * (lane >> 4) / BR : 0;  // the lane's column of the group
+      const int64_t co = col_out[NP * col + eb];
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int row = 16 * mt + 4 * (lane >> 4) + v - (PK ? (lane >> 5) * kPackRows : 0);
+        const int row = 16 * mt + 4 * (lane >> 4) + v - eb * BR;
         if (co >= 0 && row < KR) {
           int64_t el = co + (int64_t)row * P.s_out_t;
           ((OB_GLOBAL uint16_t*)P.dbg_res)[(el * 2) * R + i] = (uint16_t)(rrv[v] < 0.0f ? rrv[v] + mf : rrv[v]);
@@ -619,8 +622,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   const OB_CONST CrtConsts& C = *(const OB_CONST CrtConsts*)P.crt;
   const v16f seed = phase_a_seed(C.seedT_c, lane >> 5);
   const typename EP::LiftK LK = EP::load_lift(C, false);
-  // PK: lanes 0-31 hold rows 0-7 (the pair's first column), lanes 32-63 rows 8-15
-  const int ecol = PK ? 2 * col + (lane >> 5) : col;
+  // packed: lane l holds rows 4 (l / 16) .. + 3, i.e. column 4 (l / 16) / BR of the group
+  // (NP = 2: lanes 0-31 rows 0-7, 32-63 rows 8-15; NP = 4: lanes 16 b .. 16 b + 15 column b)
+  const int eb = PK ? 4 * (lane >> 4) / BR : 0;
+  const int ecol = NP * col + eb;
   const int64_t co = col_out[ecol];
   const int ex = cexp[ecol] - 2 * (TT::PREC - 1) + P.extra_shift;
   typename TT::T re_part = 0;
@@ -654,7 +659,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
     if (prt == 0) {
       re_part = y;
     } else {
-      const int row = 16 * mt + 4 * (lane >> 4) + v - (PK ? (lane >> 5) * kPackRows : 0);
+      const int row = 16 * mt + 4 * (lane >> 4) + v - eb * BR;
       if (co >= 0 && row < KR) {
         typename TT::V2 z;
         z.x = re_part;
@@ -665,18 +670,18 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   }
 }
 
-template <int SUB, int TGT, int KMAX, bool FULL, bool H0, bool PK>
+template <int SUB, int TGT, int KMAX, bool FULL, bool H0, int NP>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_stage_kernel(
     const StageParams P) {
   int64_t c, g;
   grid_tile(P, c, g);
-  stage_tile<SUB, TGT, KMAX, FULL, H0, PK>(P, c, g);
+  stage_tile<SUB, TGT, KMAX, FULL, H0, NP>(P, c, g);
 }
 
 // Batched stage: one workgroup per tile of the members of one Bailey pass
 // whose contraction length falls in this kernel's class.  tmember[t] is the
 // member that owns tile t, descs[d] its stage and first[d] its first tile.
-template <int SUB, int TGT, int KMAX, bool FULL, bool PK>
+template <int SUB, int TGT, int KMAX, bool FULL, int NP>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ first,
                                                             const uint16_t* __restrict__ tmember, int64_t total) {
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
   const StageParams P = descs[d];
   int64_t c, g;
   decode_tile(P, t - first[d], c, g);
-  stage_tile<SUB, TGT, KMAX, FULL, false, PK>(P, c, g);
+  stage_tile<SUB, TGT, KMAX, FULL, false, NP>(P, c, g);
 }
 
 // ---- plan-time conversion of signed digit planes to E4M3 ----
@@ -704,35 +709,38 @@ __global__ void digits_to_fp8_kernel(uint8_t* p, int64_t n4) {
 // ---- host-side launch helpers ----
 // Dynamic LDS of a stage tile: the packed variant holds column tables for
 // twice the columns.
-template <int SUB, int TGT, int KMAX, bool PK>
+template <int SUB, int TGT, int KMAX, int NP>
 static int stage_lds_bytes(int K) {
-  return StageLds<SUB, TGT, KMAX>::bytes(K) + (PK ? Shape<KMAX>::NCOL * 20 : 0);
+  return StageLds<SUB, TGT, KMAX>::bytes(K) + (NP - 1) * Shape<KMAX>::NCOL * 20;
 }
 
-template <int SUB, int TGT, int KMAX, bool FULL, bool H0, bool PK = false>
+template <int SUB, int TGT, int KMAX, bool FULL, bool H0, int NP = 1>
 static hipError_t launch_stage_t(const StageParams& P, dim3 grid, hipStream_t st) {
-  int lds = stage_lds_bytes<SUB, TGT, KMAX, PK>(P.K);
+  int lds = stage_lds_bytes<SUB, TGT, KMAX, NP>(P.K);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX, FULL, H0, PK>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_kernel<SUB, TGT, KMAX, FULL, H0, NP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL, H0, PK>), grid, dim3(kThreads), lds, st, P);
+  hipLaunchKernelGGL((ob_stage_kernel<SUB, TGT, KMAX, FULL, H0, NP>), grid, dim3(kThreads), lds, st, P);
   return hipGetLastError();
 }
 
 // Full-length variants for the default substrate at K = 12, 16 and 32 and
-// the packed two-column tile for 4 < K <= 8; everything else takes the
-// general kernel.
+// the packed tiles for K <= 8 (four columns per tile up to K = 4, two up to
+// K = 8); everything else takes the general kernel.
 template <int SUB, int TGT, bool H0>
 static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st) {
   constexpr bool F = SUB == SUB_FP16;
   int K = P.K;
-  if (K <= 4) return launch_stage_t<SUB, TGT, 4, false, H0>(P, grid, st);
+  if (K <= 4) {
+    if constexpr (F) return launch_stage_t<SUB, TGT, 16, true, H0, 4>(P, grid, st);
+    else return launch_stage_t<SUB, TGT, 4, false, H0>(P, grid, st);
+  }
   if (K <= 8) {
-    if constexpr (F) return launch_stage_t<SUB, TGT, 2 * kPackRows, true, H0, true>(P, grid, st);
+    if constexpr (F) return launch_stage_t<SUB, TGT, 16, true, H0, 2>(P, grid, st);
     else return launch_stage_t<SUB, TGT, 8, false, H0>(P, grid, st);
   }
   if (K <= 12) {
@@ -763,18 +771,18 @@ hipError_t launch_stage(int sub, int tgt, bool h0, const StageParams& P, dim3 gr
                   : launch_stage_k<SUB_FP8, 1, false>(P, grid, st);
 }
 
-template <int SUB, int KMAX, bool FULL, bool PK = false>
+template <int SUB, int KMAX, bool FULL, int NP = 1>
 static hipError_t launch_batch_t(const StageParams* descs, const int64_t* first, const uint16_t* tmember,
                                  int64_t total, hipStream_t st) {
-  int lds = stage_lds_bytes<SUB, 0, KMAX, PK>(KMAX);
+  int lds = stage_lds_bytes<SUB, 0, KMAX, NP>(KMAX);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_batch_kernel<SUB, 0, KMAX, FULL, PK>,
+    hipError_t e = hipFuncSetAttribute((const void*)ob_batch_kernel<SUB, 0, KMAX, FULL, NP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX, FULL, PK>), dim3((unsigned)total), dim3(kThreads), lds, st,
+  hipLaunchKernelGGL((ob_batch_kernel<SUB, 0, KMAX, FULL, NP>), dim3((unsigned)total), dim3(kThreads), lds, st,
                      descs, first, tmember, total);
   return hipGetLastError();
 }
@@ -794,9 +802,11 @@ static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, 
                                  const uint16_t* tmember, int64_t total, hipStream_t st) {
   constexpr bool F = SUB == SUB_FP16;
   switch (kmax) {
-    case 4: return launch_batch_t<SUB, 4, false>(descs, first, tmember, total, st);
+    case 4:  // FP16: the packed four-column tile
+      if constexpr (F) return launch_batch_t<SUB, 16, true, 4>(descs, first, tmember, total, st);
+      else return launch_batch_t<SUB, 4, false>(descs, first, tmember, total, st);
     case 8:  // FP16: the packed two-column tile for every K of the class
-      if constexpr (F) return launch_batch_t<SUB, 2 * kPackRows, true, true>(descs, first, tmember, total, st);
+      if constexpr (F) return launch_batch_t<SUB, 16, true, 2>(descs, first, tmember, total, st);
       else return launch_batch_t<SUB, 8, false>(descs, first, tmember, total, st);
     case 12:
       return F && full ? launch_batch_t<SUB, 12, F>(descs, first, tmember, total, st)
@@ -820,7 +830,7 @@ hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, 
 
 // Columns per workgroup of the stage kernel for contraction length K.
 int stage_cols_per_wg(int K, int sub) {
-  if (fp16_packed(sub, K)) return 2 * Shape<2 * kPackRows>::NCOL;
+  if (fp16_pack(sub, K) > 1) return fp16_pack(sub, K) * Shape<16>::NCOL;
   return K <= 16 ? Shape<16>::NCOL : Shape<32>::NCOL;
 }
 

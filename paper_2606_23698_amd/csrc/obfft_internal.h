@@ -14,12 +14,14 @@ constexpr int kTapStride = 40;     // uint32 words per output in the CRT debug t
 enum Substrate { SUB_FP8 = 0, SUB_INT8 = 1, SUB_FP16 = 2, SUB_AUTO = 3 };
 
 // Column packing of short contractions on the FP16 substrate: a stage with
-// 4 < K <= 8 runs as a block-diagonal 16 x 16 product, rows and contraction
-// slots 0..7 of one column and 8..15 of the next, so that the 16-row MFMA
-// tile and the per-row CRT epilogue carry two columns instead of one
-// column and eight dead rows.
-__host__ __device__ constexpr bool fp16_packed(int sub, int K) { return sub == SUB_FP16 && K > 4 && K <= 8; }
-constexpr int kPackRows = 8;  // rows (and contraction slots) per packed column
+// K <= 8 runs as a block-diagonal 16 x 16 product with np = 16 / 8 = 2
+// (4 < K <= 8) or 16 / 4 = 4 (K <= 4) diagonal blocks, rows and contraction
+// slots b 16/np .. (b+1) 16/np - 1 belonging to column b of the group, so that
+// the 16-row MFMA tile and the per-row CRT epilogue carry np columns instead
+// of one column and 16 - K dead rows.  1: no packing.
+__host__ __device__ constexpr int fp16_pack(int sub, int K) {
+  return sub != SUB_FP16 ? 1 : K <= 4 ? 4 : K <= 8 ? 2 : 1;
+}
 
 // FP16 substrate: the first kFp16Split[precision] moduli of a set enter the
 // residue GEMM as two radix-128 limbs per index; every later modulus as one

@@ -459,10 +459,12 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
                           int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L) {
   int K = stage == 1 ? (int)q : (int)p;
   int G = stage == 1 ? 1 : (int)q;
-  // packed FP16 tiles: the planes are the block-diagonal diag(F, F) with F
-  // at rows and slots 0.. and kPackRows.. of a 16 x 16 matrix
-  const bool pk = fp16_packed(substrate, K);
-  const int KV = pk ? 2 * kPackRows : K;
+  // packed FP16 tiles: the planes are the block-diagonal diag(F, ..., F) of
+  // np blocks of 16 / np rows and slots in a 16 x 16 matrix
+  const int np = fp16_pack(substrate, K);
+  const bool pk = np > 1;
+  const int BR = 16 / np;
+  const int KV = pk ? 16 : K;
   int MT = (KV + 15) / 16;
   int bpl, fmax, chmax;
   if (substrate == SUB_INT8) { bpl = 16; fmax = 2; chmax = (2 * K + 63) / 64; }
@@ -503,10 +505,10 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
                   int slot = 32 * ch + 8 * (lane / 16) + j;
                   int s = split ? slot / 2 : slot, e = split ? slot % 2 : 0;
                   int val = 0;
-                  if (pk) {  // block (t / kPackRows, s / kPackRows) is F on the diagonal, else 0
-                    const bool diag = t / kPackRows == s / kPackRows;
-                    t %= kPackRows;
-                    s = diag ? s % kPackRows : K;
+                  if (pk) {  // block (t / BR, s / BR) is F on the diagonal, else 0
+                    const bool diag = t / BR == s / BR;
+                    t %= BR;
+                    s = diag ? s % BR : K;
                   }
                   if (t < K && s < K) {
                     int a = cval[(form * K + t) * K + s];
