@@ -152,3 +152,77 @@ int oracle_dd_fft3(const double* in, double* out, const int64_t* n, const double
   }
   return 0;
 }
+
+/* ---- exported: sampled lines (the cost cone of a few outputs of a large transform) ----
+ * Both routines take and return double-double complex values, four doubles
+ * per element (re_hi, re_lo, im_hi, im_lo), so that a chain of them (one
+ * output position of every line of the first axis, then of the second, then
+ * the whole third-axis line) never rounds to binary64 in between.  The
+ * definition is the same separable DFT as above; only the outputs that the
+ * sampled line depends on are evaluated. */
+
+typedef struct {
+  const double* in;
+  int in_z;  /* input is complex binary64 (re, im) rather than double-double */
+  ddc* out;
+  int64_t N, k, begin, end;
+  const ddc* tw;
+} dd_cone_job;
+
+static void* dd_cone_worker(void* arg) {
+  dd_cone_job* J = (dd_cone_job*)arg;
+  int64_t N = J->N;
+  for (int64_t line = J->begin; line < J->end; line++) {
+    ddc acc = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int64_t j = 0; j < N; j++) {
+      ddc x;
+      if (J->in_z) {
+        const double* z = J->in + 2 * (line * N + j);
+        x.re.hi = z[0]; x.re.lo = 0.0; x.im.hi = z[1]; x.im.lo = 0.0;
+      } else {
+        x = ((const ddc*)J->in)[line * N + j];
+      }
+      acc = ddc_add(acc, ddc_mul(J->tw[(j * J->k) % N], x));
+    }
+    J->out[line] = acc;
+  }
+  return NULL;
+}
+
+/* out[l] = sum_j in[l N + j] w_N^{j k}: output position k of the DFT of every
+ * contiguous length-N line (direct sum, j ascending).  in_z = 1: the input is
+ * complex binary64 (two doubles per element), else double-double. */
+int oracle_dd_lines_at(const double* in, int in_z, double* out, int64_t nlines, int64_t N, int64_t k,
+                       const double* tw, int nthreads) {
+  if (N < 1 || k < 0 || k >= N) return -1;
+  if (nthreads < 1) nthreads = 1;
+  int nt = nthreads;
+  if (nt > nlines) nt = (int)nlines;
+  if (nt < 1) return 0;
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nt);
+  dd_cone_job* jobs = (dd_cone_job*)malloc(sizeof(dd_cone_job) * nt);
+  for (int t = 0; t < nt; t++) {
+    jobs[t].in = in;
+    jobs[t].in_z = in_z;
+    jobs[t].out = (ddc*)out;
+    jobs[t].N = N;
+    jobs[t].k = k;
+    jobs[t].begin = nlines * t / nt;
+    jobs[t].end = nlines * (t + 1) / nt;
+    jobs[t].tw = (const ddc*)tw;
+    pthread_create(&th[t], NULL, dd_cone_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  free(th); free(jobs);
+  return 0;
+}
+
+/* The whole length-N DFT of every contiguous line, double-double in and out. */
+int oracle_dd_lines(const double* in, double* out, int64_t nlines, int64_t N, const double* tw) {
+  if (N < 1) return -1;
+  ddc* s = (ddc*)malloc(sizeof(ddc) * N);
+  for (int64_t line = 0; line < nlines; line++)
+    fft_rec((const ddc*)in + line * N, 1, (ddc*)out + line * N, N, (const ddc*)tw, N, s);
+  free(s);
+  return 0;
+}

@@ -2,6 +2,8 @@
 
 ``fft3_exact``  -- ORACLE-X: the exact-pipeline transform (exact.c)
 ``fft3_dd``     -- ORACLE-DD: the double-double separable DFT (dd.c)
+``dd_cone_lines`` -- ORACLE-DD on sampled final-axis lines of a large
+                   transform (the cost cone of each line, in double-double)
 ``line_stage``  -- one stage of one line with the exact Re/Im integers, the
                    column exponents and the packed outputs (checkpoints)
 ``pack``        -- the single correctly rounded conversion, exposed for pins
@@ -43,6 +45,11 @@ def lib():
         L.oracle_lines_at.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int64, _I64P, ctypes.c_int, ctypes.c_int64,
                                       ctypes.c_int]
+        L.oracle_dd_lines_at.restype = ctypes.c_int
+        L.oracle_dd_lines_at.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int64, _DP, ctypes.c_int]
+        L.oracle_dd_lines.restype = ctypes.c_int
+        L.oracle_dd_lines.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, _DP]
         L.oracle_pack_hilo.restype = ctypes.c_double
         L.oracle_pack_hilo.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -101,6 +108,68 @@ def fft3_dd(x, inverse=False, nthreads=None):
     hi = out[..., 0] + 1j * out[..., 2]
     lo = out[..., 1] + 1j * out[..., 3]
     return hi, lo
+
+
+def _to_dd(x):
+    """complex128 array -> float64 [..., 4] double-double (re_hi, re_lo, im_hi, im_lo)."""
+    x = np.asarray(x, dtype=np.complex128)
+    d = np.zeros(x.shape + (4,), dtype=np.float64)
+    d[..., 0] = x.real
+    d[..., 2] = x.imag
+    return d
+
+
+def dd_lines_at(xd, N, k, inverse=False, nthreads=None):
+    """Output position k of the double-double DFT of every contiguous length-N
+    line of xd: float64 [..., N, 4] double-double values, or complex [..., N]
+    binary64 values.  Returns float64 [..., 4]."""
+    if np.iscomplexobj(xd):
+        xd = np.ascontiguousarray(xd, dtype=np.complex128)
+        assert xd.shape[-1] == N
+        in_z, lead = 1, xd.shape[:-1]
+    else:
+        xd = np.ascontiguousarray(xd, dtype=np.float64)
+        assert xd.shape[-2:] == (N, 4)
+        in_z, lead = 0, xd.shape[:-2]
+    nl = int(np.prod(lead))
+    out = np.empty(lead + (4,), dtype=np.float64)
+    tw = np.ascontiguousarray(_roots.dd_twiddles(int(N), inverse))
+    rc = lib().oracle_dd_lines_at(xd.ctypes.data, in_z, out.ctypes.data, nl, N, k, _ptr(tw, _DP),
+                                  nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad position")
+    return out
+
+
+def dd_lines(xd, N, inverse=False):
+    """The whole double-double DFT of every contiguous length-N line of xd (float64 [..., N, 4])."""
+    xd = np.ascontiguousarray(xd, dtype=np.float64)
+    assert xd.shape[-2:] == (N, 4)
+    out = np.empty_like(xd)
+    tw = np.ascontiguousarray(_roots.dd_twiddles(int(N), inverse))
+    lib().oracle_dd_lines(xd.ctypes.data, out.ctypes.data, xd.size // (4 * N), N, _ptr(tw, _DP))
+    return out
+
+
+def dd_cone_lines(x, samples, inverse=False, nthreads=None):
+    """ORACLE-DD on sampled lines along axis 0 of the 3-D DFT of x (n1, n2, n3).
+
+    samples: iterable of (k2, k3).  Line (k2, k3) is X[:, k2, k3]; it depends
+    on every input: output k3 of all n1 n2 axis-3 lines, then output k2 of
+    the n1 axis-2 lines, then the whole axis-1 transform, all in
+    double-double.  Returns {(k2, k3): (hi, lo)} with complex128 hi and lo.
+    """
+    x = np.asarray(x)
+    n1, n2, n3 = x.shape
+    samples = list(samples)
+    out = {}
+    for k3 in sorted({k3 for _, k3 in samples}):
+        a3 = dd_lines_at(x.reshape(n1 * n2, n3), n3, k3, inverse, nthreads).reshape(n1, n2, 4)
+        for k2 in sorted({k2 for k2, kk in samples if kk == k3}):
+            a2 = dd_lines_at(a3, n2, k2, inverse, nthreads)            # [n1, 4]
+            a1 = dd_lines(a2.reshape(1, n1, 4), n1, inverse)[0]         # [n1, 4]
+            out[(k2, k3)] = (a1[:, 0] + 1j * a1[:, 2], a1[:, 1] + 1j * a1[:, 3])
+    return out
 
 
 def _join(hi, lo):

@@ -11,8 +11,12 @@ all real parts drawn before all imaginary parts):
 * batch_shapes(seed=3): 64 shapes, each extent drawn from
   {64, 96, 128, 192, 256}, then the member inputs from the same stream.
 
+``uniform_chunked`` and ``uniform_to_device`` produce exactly ``uniform``'s
+values (the same PCG64 stream, consumed in order) in bounded-size pieces, for
+the 1024^3 and 512^3 workloads: the first builds the host array, the second
+fills a device tensor without holding the whole array on the host.
 ``device_uniform`` draws the same distribution with torch's seeded device
-generator for sizes where a host stream is too slow (the 1024^3 bench input).
+generator (not the host stream) for auxiliary inputs that no oracle reads.
 """
 import numpy as np
 
@@ -27,6 +31,51 @@ def uniform(shape, seed, dtype=np.complex128):
     out.real = re
     out.imag = im
     return out.astype(dtype)
+
+
+_CHUNK = 1 << 24
+
+
+def _stream_parts(shape, seed, chunk, rng=None):
+    """Yields (part, start, values): part 0 = real parts, 1 = imaginary parts,
+    C order, in the order uniform() draws them (from `rng` if given, else a
+    fresh stream of `seed`)."""
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(seed) if rng is None else rng
+    for part in (0, 1):
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            yield part, a, rng.uniform(-1.0, 1.0, b - a)
+
+
+def uniform_chunked(shape, seed, dtype=np.complex128, chunk=_CHUNK):
+    """uniform(shape, seed) built chunk by chunk (identical values)."""
+    out = np.empty(int(np.prod(shape)), dtype=dtype)
+    for part, a, v in _stream_parts(shape, seed, chunk):
+        if part == 0:
+            out.real[a:a + len(v)] = v
+        else:
+            out.imag[a:a + len(v)] = v
+    return out.reshape(shape)
+
+
+def uniform_to_device(shape, seed, device="cuda", dtype=None, chunk=_CHUNK, rng=None):
+    """A device tensor holding uniform(shape, seed) (identical values), filled
+    chunk by chunk from the host stream."""
+    import torch
+    dtype = dtype or torch.complex128
+    x = torch.empty(tuple(shape), dtype=dtype, device=device)
+    xr = torch.view_as_real(x).view(-1, 2)
+    real_dtype = torch.float64 if dtype == torch.complex128 else torch.float32
+    for part, a, v in _stream_parts(shape, seed, chunk, rng):
+        xr[a:a + len(v), part].copy_(torch.from_numpy(v).to(real_dtype))
+    return x
+
+
+def batch_to_device(seed=3, count=64, device="cuda"):
+    """batch_inputs(seed, count) as device tensors (identical values)."""
+    shapes, rng = batch_shapes(seed, count)
+    return shapes, [uniform_to_device(s, None, device, rng=rng) for s in shapes]
 
 
 def wide_range(shape, seed):

@@ -56,8 +56,7 @@ def test_batch_64_uneven_workload(gpu):
     and the three smallest members equal the oracle's exact pipeline."""
     from oracle import exact as ox
     from paper_2606_23698_amd import api
-    shapes, _ = inputs.batch_shapes(3, 64)
-    xs = [inputs.device_uniform(s, 3 + i, device=gpu) for i, s in enumerate(shapes)]
+    shapes, xs = inputs.batch_to_device(3, 64, device=gpu)
     bp = api.BatchPlan(shapes)
     outs = bp.forward(xs)
     torch.cuda.synchronize()
