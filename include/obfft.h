@@ -19,9 +19,10 @@
  *   - Forward transform: Y[k] = sum_j X[j] exp(-2 pi i j.k / n), unnormalised.
  *     Inverse: exp(+2 pi i ...) and the factor 1/(n1 n2 n3).  Adjoint:
  *     exp(+2 pi i ...), unnormalised (the Hermitian adjoint of forward).
- *   - Axes are processed n3, then n2, then n1; stage 1 contracts over j2
- *     (length q), stage 2 over j1 (length p).  Factorisation and axis order
- *     change output bits; both are fixed by the plan.
+ *   - Axes are processed n3, then n2, then n1 unless the plan's axis_order
+ *     says otherwise; stage 1 contracts over j2 (length q), stage 2 over j1
+ *     (length p).  Factorisation and axis order change output bits; both are
+ *     fixed by the plan.
  *   - `in`/`out` are DEVICE pointers owned by the caller; in == out is
  *     allowed, partial overlap is rejected with OBFFT_INVALID_VALUE.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
@@ -50,7 +51,8 @@ typedef enum {
   OBFFT_UNSUPPORTED_SIZE = 2,     /* an extent with no admissible p x q split, or
                                      n1 n2 n3 / q >= 2^31 on some axis */
   OBFFT_CAPACITY_EXCEEDED = 3,    /* log2 M <= 1 + log2 K + 2(k+1) (Sec. 2, Eq. capacity) */
-  OBFFT_NONFINITE_INPUT = 4,      /* reserved: non-finite input values */
+  OBFFT_NONFINITE_INPUT = 4,      /* a kernel read an Inf or NaN input value (reported by
+                                     obfft_last_error after the stream has synchronised) */
   OBFFT_ALLOC_FAILED = 5,         /* device or host allocation failed */
   OBFFT_HIP_ERROR = 6,            /* a HIP runtime call failed */
   OBFFT_UNSUPPORTED_DEVICE = 7,   /* the current device is not gfx950 */
@@ -106,7 +108,11 @@ typedef struct {
                                its L2.  0 = library default (8 when it divides q); else one of
                                1, 2, 4, 8, 16, 32 (else OBFFT_INVALID_VALUE), used where it
                                divides q of that axis.  Changes speed only, never results. */
-  int reserved[6];
+  int axis_order[3];        /* the axes in execution order (0 = n1), a permutation of
+                               {0, 1, 2}; all zero = library default {2, 1, 0} (n3, then n2,
+                               then n1).  Changes output bits (every axis pass rounds once
+                               per stage), so the plan records it. */
+  int reserved[3];
 } obfft_options_t;
 
 typedef struct {
@@ -162,6 +168,30 @@ obfft_status_t fft3d_c2c_inverse(obfft_plan_t plan, const void* in, void* out, v
  * Works on any FP64 plan; uses the plan's workspace. */
 obfft_status_t fft3d_z2z_native_forward(obfft_plan_t plan, const void* in, void* out, void* stream);
 obfft_status_t fft3d_z2z_native_inverse(obfft_plan_t plan, const void* in, void* out, void* stream);
+
+/* Debug tap of the fused stage kernel (the checkpoints of Alg. 2 for one
+ * line).  Runs stage `stage` (1 or 2) of axis `axis` (0 = n1), direction 0
+ * (forward) or 1 (conjugate), on the device array `in` (natural order for
+ * stage 1, Y' slots for stage 2, as obfft_stage) into the device array `out`
+ * (not aliasing in), with the debug variant of the kernel, then copies the
+ * epilogue records of every output of line `line` to host memory and returns
+ * after synchronising `stream`.  A line of axis a is (outer o, inner i) with
+ * line = o * inner + i, inner = product of the faster extents,
+ * 0 <= line < n1 n2 n3 / n_a.  host_dump: uint32 [n_a][2 (Re, Im)][64]; the
+ * record of output slot t (the slot order of the stage, as obfft_stage) is:
+ *   [0, S)      Phase-A slice sums P_s (int32, Eq. slicing)
+ *   [16, 16+T)  Phase-A lift sums Z_t (int32, Sec. 5.1)
+ *   [24, 29)    E = sum_s 256^s P_s, two's complement, little-endian words
+ *   29          zhat = round-half-up(2^-48 sum_t 256^t Z_t) (int32)
+ *   [30, 34)    R = E - zhat M, the exact stage integer (two's complement)
+ *   34          the pack exponent: the output is RNE(R 2^exp) (int32)
+ *   35, 36      the output value's bits (binary64 low/high word; binary32 in 35)
+ *   [40, 40+r)  the residues v_k that entered Phase A (int32; the stage
+ *               kernels take centred residues, |v_k| <= m_k/2 + 2)
+ * The stage output is written to `out` as by obfft_stage.  Allocates a small
+ * device buffer per call.  Bad arguments return OBFFT_INVALID_VALUE. */
+obfft_status_t obfft_debug_tap(obfft_plan_t plan, int axis, int stage, int direction, int64_t line,
+                               const void* in, void* out, void* host_dump, void* stream);
 
 /* One Bailey stage of one axis (unit-level access to the fused kernel).
  * stage 1 reads natural order and writes Y' with Y'_{j1,k2} at slot
@@ -274,8 +304,16 @@ obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, vo
 obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph);
 
 const char* obfft_status_string(obfft_status_t status);
-/* The status of the last failed call on this plan (OBFFT_SUCCESS if none). */
+/* The status of the last failed call on this plan (OBFFT_SUCCESS if none),
+ * or OBFFT_NONFINITE_INPUT when a kernel of this plan has read an Inf or NaN
+ * input value since the flag was last read: the kernels raise a device flag
+ * and run to completion (the affected outputs are meaningless), and this
+ * call reads the flag with a blocking copy, so call it after synchronising
+ * the stream.  Reading clears the device flag; the status stays until
+ * obfft_clear_error. */
 obfft_status_t obfft_last_error(obfft_plan_t plan);
+/* Resets the plan's recorded status and device flag to OBFFT_SUCCESS. */
+obfft_status_t obfft_clear_error(obfft_plan_t plan);
 
 #ifdef __cplusplus
 }

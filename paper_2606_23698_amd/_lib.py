@@ -26,7 +26,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("substrate", ctypes.c_int), ("p", ctypes.c_int * 3),
                 ("q", ctypes.c_int * 3), ("n_moduli_override", ctypes.c_int),
                 ("moduli_override", ctypes.POINTER(ctypes.c_int32)), ("reduction", ctypes.c_int),
-                ("group_block", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("group_block", ctypes.c_int), ("axis_order", ctypes.c_int * 3), ("reserved", ctypes.c_int * 3)]
 
 
 class TapsLayout(ctypes.Structure):
@@ -66,6 +66,7 @@ def lib():
         "fft3d_z2z_native_forward": (i32, [vp, vp, vp, vp]),
         "fft3d_z2z_native_inverse": (i32, [vp, vp, vp, vp]),
         "obfft_stage": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
+        "obfft_debug_tap": (i32, [vp, i32, i32, i32, i64, vp, vp, vp, vp]),
         "obfft_crt_reconstruct": (i32, [i32, i64, vp, vp, vp, vp, vp]),
         "obfft_crt_reconstruct_method": (i32, [i32, i32, i64, vp, vp, vp, vp]),
         "obfft_taps_layout": (None, [P(TapsLayout)]),
@@ -77,6 +78,7 @@ def lib():
         "obfft_batch_set_graph": (i32, [vp, i32]),
         "obfft_status_string": (ctypes.c_char_p, [i32]),
         "obfft_last_error": (i32, [vp]),
+        "obfft_clear_error": (i32, [vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -101,7 +103,8 @@ def check(status, what=""):
 EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", "obfft_plan_info",
             "obfft_workspace_size", "obfft_set_workspace", "obfft_plan_roots", "fft3d_z2z_forward",
             "fft3d_z2z_inverse", "fft3d_z2z_adjoint", "fft3d_c2c_forward", "fft3d_c2c_inverse",
-            "fft3d_z2z_native_forward", "fft3d_z2z_native_inverse", "obfft_stage",
+            "fft3d_z2z_native_forward", "fft3d_z2z_native_inverse", "obfft_stage", "obfft_debug_tap",
             "obfft_crt_reconstruct", "obfft_crt_reconstruct_method", "obfft_taps_layout", "obfft_mfma_probe",
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
-            "obfft_batch_forward", "obfft_batch_set_graph", "obfft_status_string", "obfft_last_error"]
+            "obfft_batch_forward", "obfft_batch_set_graph", "obfft_status_string", "obfft_last_error",
+            "obfft_clear_error"]

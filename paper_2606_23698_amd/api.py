@@ -49,13 +49,17 @@ def _check_dev(t, dtype, numel=None, name="tensor"):
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
 
-def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal", group_block=0):
+def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal", group_block=0,
+            axis_order=None):
     opt = L.Options()
     L.lib().obfft_options_default(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
     opt.substrate = SUBSTRATES[substrate]
     opt.reduction = REDUCTIONS[reduction]
     opt.group_block = int(group_block)
+    if axis_order is not None:
+        for k, a in enumerate(axis_order):
+            opt.axis_order[k] = int(a)
     if pq is not None:
         for a, (p, q) in enumerate(pq):
             opt.p[a] = int(p)
@@ -72,12 +76,12 @@ class Plan:
     """An Ozaki-Bailey 3-D FFT plan for one shape on the current device."""
 
     def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal",
-                 group_block=0):
+                 group_block=0, axis_order=None):
         self.shape = tuple(int(n) for n in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must have three extents")
         self.precision = precision
-        opt, keep = options(precision, substrate, pq, moduli, reduction, group_block)
+        opt, keep = options(precision, substrate, pq, moduli, reduction, group_block, axis_order)
         h = ctypes.c_void_p()
         L.check(L.lib().obfft_plan_create(ctypes.byref(h), *self.shape, ctypes.byref(opt)),
                 "obfft_plan_create")
@@ -162,6 +166,29 @@ class Plan:
                                     _stream(stream)), "obfft_stage")
         return out
 
+    def debug_tap(self, axis, stage, line, x, out=None, direction=0, stream=None):
+        """Epilogue records of one line of one stage (see obfft_debug_tap):
+        returns (stage output, uint32 array [n_axis, 2, 64])."""
+        x = _materialise(x)
+        _check_dev(x, self.cdtype, name="input")
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"input shape {tuple(x.shape)} != plan shape {self.shape}")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_dev(out, self.cdtype, x.numel(), name="output")
+        dump = np.zeros((self.shape[axis], 2, 64), dtype=np.uint32)
+        L.check(L.lib().obfft_debug_tap(self._h, axis, stage, direction, int(line), _ptr(x), _ptr(out),
+                                        ctypes.c_void_p(dump.ctypes.data), _stream(stream)), "obfft_debug_tap")
+        return out, dump
+
+    def last_error(self):
+        """The plan's status: the last failed call, or OBFFT_NONFINITE_INPUT when a
+        kernel read an Inf or NaN (synchronise the stream first)."""
+        return int(L.lib().obfft_last_error(self._h))
+
+    def clear_error(self):
+        L.check(L.lib().obfft_clear_error(self._h), "obfft_clear_error")
+
 
 class BatchPlan:
     """Several independent FP64 transforms of (possibly) different shapes."""
@@ -175,6 +202,9 @@ class BatchPlan:
                                                 arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                                 ctypes.byref(opt)), "obfft_batch_plan_create")
         self._h = h
+
+    def last_error(self):
+        return int(L.lib().obfft_last_error(self._h))
 
     def set_graph(self, use_graph):
         L.check(L.lib().obfft_batch_set_graph(self._h, int(bool(use_graph))), "obfft_batch_set_graph")

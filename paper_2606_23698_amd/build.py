@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libobfft.so")
-SOURCES = ["csrc/ob_kernels.hip", "csrc/crt_kernels.hip", "csrc/probe.hip", "csrc/native.hip", "csrc/capi.hip", "csrc/plan_math.cpp"]
-HEADERS = ["csrc/ob_device.h", "csrc/ob_recon.h", "csrc/crt_methods.h", "csrc/obfft_internal.h", "csrc/plan_math.h"]
+SOURCES = ["csrc/ob_kernels.hip", "csrc/ob_tap.hip", "csrc/crt_kernels.hip", "csrc/probe.hip", "csrc/native.hip", "csrc/capi.hip", "csrc/plan_math.cpp"]
+HEADERS = ["csrc/ob_stage.h", "csrc/ob_device.h", "csrc/ob_recon.h", "csrc/crt_methods.h", "csrc/obfft_internal.h", "csrc/plan_math.h"]
 
 
 def build(verbose=False, jobs=4):

@@ -14,6 +14,7 @@
 
 namespace obfft {
 hipError_t launch_stage(int sub, int tgt, bool h0, const StageParams& P, dim3 grid, hipStream_t st);
+hipError_t launch_stage_tap(int sub, int tgt, bool h0, const StageParams& P, dim3 grid, hipStream_t st);
 hipError_t launch_crt(int tgt, int64_t n, const uint16_t* residues, const int* exps, void* out,
                       uint32_t* taps, const uint16_t* phaseA, const CrtConsts* C, hipStream_t st);
 hipError_t launch_crt_ablation(int tgt, int method, int64_t n, const uint16_t* residues, const int* exps,
@@ -48,6 +49,7 @@ struct obfft_plan_s {
   int precision = 0, substrate = SUB_FP8, kbits = 53;
   int reduction = OBFFT_RED_RECIPROCAL;
   int group_block = 0;  // 0: the library's choice
+  int order[3] = {2, 1, 0};  // axes in execution order (0 = n1)
   ModSet H;
   CrtConsts C;
   ModConsts MC;
@@ -57,6 +59,7 @@ struct obfft_plan_s {
   uint16_t* d_phaseA = nullptr;
   const ModConsts* d_mc = nullptr;    // device copies of MC and C
   const CrtConsts* d_crt = nullptr;
+  uint32_t* d_flags = nullptr;        // device word: bit 0 = a non-finite input was read
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
@@ -174,6 +177,8 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   // the fold-and-add reduction is an ablation of the default FP64 path
   plan->reduction = opt->reduction;
   plan->group_block = opt->group_block;
+  if (opt->axis_order[0] | opt->axis_order[1] | opt->axis_order[2])
+    for (int k = 0; k < 3; k++) plan->order[k] = opt->axis_order[k];
   if (opt->reduction == OBFFT_RED_H0 && (sub != OBFFT_SUB_FP16 || plan->precision != OBFFT_PREC_FP64))
     return OBFFT_INVALID_VALUE;
   int64_t kmax = 0;
@@ -247,6 +252,11 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   if (s != OBFFT_SUCCESS) return s;
   plan->d_mc = (const ModConsts*)dmc;
   plan->d_crt = (const CrtConsts*)dcr;
+  const uint32_t zero_flags[64] = {};
+  void* dfl = nullptr;
+  s = upload(plan, zero_flags, sizeof(zero_flags), &dfl);
+  if (s != OBFFT_SUCCESS) return s;
+  plan->d_flags = (uint32_t*)dfl;
   plan->ws_bytes = (size_t)(plan->n[0] * plan->n[1] * plan->n[2]) * (plan->precision ? 8 : 16);
   if (hipDeviceSynchronize() != hipSuccess) return OBFFT_HIP_ERROR;
   if (plan->precision == OBFFT_PREC_FP64) {
@@ -269,6 +279,14 @@ extern "C" obfft_status_t obfft_plan_create(obfft_plan_t* out, int64_t n1, int64
   if (opt->reduction != OBFFT_RED_RECIPROCAL && opt->reduction != OBFFT_RED_H0) return OBFFT_INVALID_VALUE;
   if (opt->group_block < 0 || opt->group_block > 32 || (opt->group_block & (opt->group_block - 1)))
     return OBFFT_INVALID_VALUE;
+  if (opt->axis_order[0] | opt->axis_order[1] | opt->axis_order[2]) {
+    int seen = 0;
+    for (int k = 0; k < 3; k++) {
+      if (opt->axis_order[k] < 0 || opt->axis_order[k] > 2) return OBFFT_INVALID_VALUE;
+      seen |= 1 << opt->axis_order[k];
+    }
+    if (seen != 7) return OBFFT_INVALID_VALUE;
+  }
   obfft_plan_t plan = new (std::nothrow) obfft_plan_s();
   if (!plan) return OBFFT_ALLOC_FAILED;
   plan->n[0] = n1;
@@ -436,6 +454,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   div_magic(stage == 1 ? p : q, &P.G_magic, &P.G_shift);
   P.mc = plan->d_mc;
   P.crt = plan->d_crt;
+  P.nf_flag = plan->d_flags;
   if (stage == 1) {
     P.K = (int)q;
     P.G = (int)p;
@@ -463,18 +482,24 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   }
 }
 
+// dbg / tap: the debug kernels' residue tap and the epilogue records of line
+// tap_line (either may be null; both null selects the production kernel).
 static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int direction, const void* in,
-                                void* out, int extra_shift, uint16_t* dbg, hipStream_t st) {
+                                void* out, int extra_shift, uint16_t* dbg, hipStream_t st,
+                                uint32_t* tap = nullptr, int64_t tap_line = -1) {
   StageParams P;
   int64_t tiles;
   stage_params(plan, axis, stage, direction, in, out, P, tiles);
   const dim3 grid = stage_grid(P, tiles);
   P.extra_shift = extra_shift;
   P.dbg_res = dbg;
+  P.dbg_tap = tap;
+  P.dbg_line = tap_line;
   if (tiles <= 0) return OBFFT_SUCCESS;
-  if (launch_stage(plan->substrate, plan->precision, plan->reduction == OBFFT_RED_H0, P, grid, st) != hipSuccess)
-    return OBFFT_HIP_ERROR;
-  return OBFFT_SUCCESS;
+  const bool h0 = plan->reduction == OBFFT_RED_H0;
+  const hipError_t e = (dbg || tap) ? launch_stage_tap(plan->substrate, plan->precision, h0, P, grid, st)
+                                    : launch_stage(plan->substrate, plan->precision, h0, P, grid, st);
+  return e == hipSuccess ? OBFFT_SUCCESS : OBFFT_HIP_ERROR;
 }
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -499,10 +524,9 @@ static obfft_status_t run_transform(obfft_plan_t plan, const void* in, void* out
       post_scale = true;
     }
   }
-  const int order[3] = {2, 1, 0};
   const void* cur = in;
   for (int k = 0; k < 3; k++) {
-    int a = order[k];
+    int a = plan->order[k];
     s = run_stage(plan, a, 1, direction, cur, plan->ws, 0, nullptr, st);
     if (s != OBFFT_SUCCESS) return s;
     s = run_stage(plan, a, 2, direction, plan->ws, out, k == 2 ? shift : 0, nullptr, st);
@@ -570,6 +594,69 @@ extern "C" obfft_status_t obfft_stage(obfft_plan_t plan, int axis, int stage, in
     return fail(plan, OBFFT_INVALID_VALUE);
   return fail(plan, run_stage(plan, axis, stage, direction, in, out, 0, (uint16_t*)residues_out,
                               (hipStream_t)stream));
+}
+
+static uint32_t float_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, sizeof(u));
+  return u;
+}
+
+// Epilogue records of one line of one stage (debug entry point): runs the
+// debug variant of the stage kernel, copies the raw records of the line to the
+// host and turns the seeded bit patterns into the values they encode.
+extern "C" obfft_status_t obfft_debug_tap(obfft_plan_t plan, int axis, int stage, int direction, int64_t line,
+                                          const void* in, void* out, void* host_dump, void* stream) {
+  if (!plan || plan->batch_count) return OBFFT_INVALID_VALUE;
+  if (axis < 0 || axis > 2 || (stage != 1 && stage != 2) || (direction != 0 && direction != 1) || !in ||
+      !out || in == out || !host_dump)
+    return fail(plan, OBFFT_INVALID_VALUE);
+  const int64_t N = plan->n[axis], total = plan->n[0] * plan->n[1] * plan->n[2];
+  if (line < 0 || line >= total / N) return fail(plan, OBFFT_INVALID_VALUE);
+  const size_t bytes = (size_t)N * 2 * kTapRecWords * sizeof(uint32_t);
+  uint32_t* d_tap = nullptr;
+  if (hipMalloc(&d_tap, bytes) != hipSuccess) return fail(plan, OBFFT_ALLOC_FAILED);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<uint32_t> raw((size_t)N * 2 * kTapRecWords);
+  obfft_status_t s = OBFFT_SUCCESS;
+  if (hipMemsetAsync(d_tap, 0xFF, bytes, st) != hipSuccess) s = OBFFT_HIP_ERROR;
+  if (s == OBFFT_SUCCESS) s = run_stage(plan, axis, stage, direction, in, out, 0, nullptr, st, d_tap, line);
+  if (s == OBFFT_SUCCESS &&
+      (hipMemcpyAsync(raw.data(), d_tap, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    s = OBFFT_HIP_ERROR;
+  (void)hipFree(d_tap);
+  if (s != OBFFT_SUCCESS) return fail(plan, s);
+  const CrtConsts& C = plan->C;
+  const int NW = C.nwords, VP = (C.S + 1) / 2;
+  const int wbits = 32 * NW;
+  const unsigned __int128 mask = NW == 4 ? ~(unsigned __int128)0 : (((unsigned __int128)1 << wbits) - 1);
+  unsigned __int128 M = 0;
+  for (int i = 0; i < NW; i++) M |= (unsigned __int128)C.M[i] << (32 * i);
+  uint32_t* dump = (uint32_t*)host_dump;
+  for (int64_t rcd = 0; rcd < 2 * N; rcd++) {
+    const uint32_t* t = &raw[(size_t)rcd * kTapRecWords];
+    uint32_t* o = dump + (size_t)rcd * kTapRecWords;
+    memset(o, 0, kTapRecWords * sizeof(uint32_t));
+    for (int q = 0; q < C.S; q++) o[kTapRecP + q] = t[kTapRecP + q] - float_bits(C.seed_c[q]);
+    for (int q = 0; q < C.T; q++) o[kTapRecZ + q] = t[kTapRecZ + q] - float_bits(C.seed_c[2 * VP + q]);
+    // E = W - zoff M (mod 2^(32 NW)), sign-extended to five words
+    unsigned __int128 W = 0, Rv = 0;
+    for (int i = 0; i < NW; i++) {
+      W |= (unsigned __int128)t[kTapRecW + i] << (32 * i);
+      Rv |= (unsigned __int128)t[kTapRecR + i] << (32 * i);
+    }
+    unsigned __int128 E = (W - (unsigned __int128)C.zoff * M) & mask;
+    const bool eneg = (E >> (wbits - 1)) & 1, rneg = (Rv >> (wbits - 1)) & 1;
+    for (int i = 0; i < 5; i++) o[kTapRecW + i] = i < NW ? (uint32_t)(E >> (32 * i)) : (eneg ? ~0u : 0u);
+    for (int i = 0; i < 4; i++) o[kTapRecR + i] = i < NW ? (uint32_t)(Rv >> (32 * i)) : (rneg ? ~0u : 0u);
+    o[kTapRecZhat] = t[kTapRecZhat] - C.zoff;
+    o[kTapRecExp] = t[kTapRecExp];
+    o[kTapRecY] = t[kTapRecY];
+    o[kTapRecY + 1] = plan->precision == OBFFT_PREC_FP64 ? t[kTapRecY + 1] : 0u;
+    for (int k = 0; k < C.r; k++) o[kTapRecRes + k] = t[kTapRecRes + k];
+  }
+  return OBFFT_SUCCESS;
 }
 
 // ---- unit-level CRT reconstruction (cached constants per precision) ----
@@ -684,7 +771,6 @@ extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* 
 // all its members (a workgroup per tile), driven by a device table of stage
 // descriptors.  The launches are captured once in a hipGraph and replayed;
 // only the table (with the callers' pointers) is re-uploaded per call.
-static const int kPassAxis[6] = {2, 2, 1, 1, 0, 0};
 static const int kPassStage[6] = {1, 2, 1, 2, 1, 2};
 
 extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
@@ -718,6 +804,16 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
   }
   bp->substrate = per[0]->substrate;
   bp->precision = OBFFT_PREC_FP64;
+  for (int k = 0; k < 3; k++) bp->order[k] = per[0]->order[k];
+  {
+    const uint32_t zero_flags[64] = {};
+    void* dfl = nullptr;
+    if (upload(bp, zero_flags, sizeof(zero_flags), &dfl) != OBFFT_SUCCESS) {
+      obfft_plan_destroy(bp);
+      return OBFFT_ALLOC_FAILED;
+    }
+    bp->d_flags = (uint32_t*)dfl;
+  }
   bp->MC = per[0]->MC;
   bp->C = per[0]->C;
   // workspace offsets (256-byte aligned)
@@ -742,7 +838,8 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     for (int i = 0; i < count; i++) {
       StageParams& P = bp->h_desc[pass * count + i];
       int64_t grid;
-      stage_params(per[i], kPassAxis[pass], kPassStage[pass], 0, nullptr, nullptr, P, grid);
+      stage_params(per[i], per[i]->order[pass / 2], kPassStage[pass], 0, nullptr, nullptr, P, grid);
+      P.nf_flag = bp->d_flags;
       cls[pass * count + i] = kclass_of(P.K);
       tiles[pass * count + i] = grid;  // the single-transform tiling is the class's
     }
@@ -902,4 +999,25 @@ extern "C" const char* obfft_status_string(obfft_status_t s) {
   return "unknown status";
 }
 
-extern "C" obfft_status_t obfft_last_error(obfft_plan_t plan) { return plan ? plan->last : OBFFT_INVALID_VALUE; }
+extern "C" obfft_status_t obfft_last_error(obfft_plan_t plan) {
+  if (!plan) return OBFFT_INVALID_VALUE;
+  if (plan->d_flags) {
+    // the device word the kernels raise on a non-finite input; reading clears it
+    uint32_t f = 0;
+    if (hipMemcpy(&f, plan->d_flags, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) return OBFFT_HIP_ERROR;
+    if (f) {
+      const uint32_t zero = 0;
+      if (hipMemcpy(plan->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return OBFFT_HIP_ERROR;
+      plan->last = OBFFT_NONFINITE_INPUT;
+    }
+  }
+  return plan->last;
+}
+
+// Clears the recorded status (and the device flag) of a plan.
+extern "C" obfft_status_t obfft_clear_error(obfft_plan_t plan) {
+  if (!plan) return OBFFT_INVALID_VALUE;
+  (void)obfft_last_error(plan);
+  plan->last = OBFFT_SUCCESS;
+  return OBFFT_SUCCESS;
+}

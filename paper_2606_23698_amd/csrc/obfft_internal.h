@@ -120,10 +120,22 @@ struct StageParams {
   int64_t amat_bytes;                  // bytes of the planes from amat on (all groups)
   int64_t amat_mod_stride;  // bytes per modulus
   const uint16_t* phaseA;   // 64 lanes x 8 FP16 operand of the Phase-A MFMA
-  uint16_t* dbg_res;        // canonical residues tap (may be null)
+  uint16_t* dbg_res;        // canonical residues tap (debug kernels only; may be null)
   const ModConsts* mc;      // device copies of the plan constants (read per use,
   const CrtConsts* crt;     // so that they do not occupy scalar registers)
+  uint32_t* nf_flag;        // set (bit 0) when a non-finite input value is read
+  uint32_t* dbg_tap;        // epilogue records of one line (debug kernels only; may be null)
+  int64_t dbg_line;         // the tapped line: outer * inner + inner index
 };
+
+// One output's epilogue record in the debug tap of a stage, as the debug
+// kernel writes it (32-bit words): the Phase-A partial patterns of the P and
+// Z slices (bits of seed_c[j] + P_j), the deposit words W = E + zoff M, the
+// lift quotient zhat + zoff, the lifted words R, the pack exponent, the
+// packed value's bits and the (centred) residues that entered Phase A.
+constexpr int kTapRecWords = 64;
+constexpr int kTapRecP = 0, kTapRecZ = 16, kTapRecW = 24, kTapRecZhat = 29, kTapRecR = 30,
+              kTapRecExp = 34, kTapRecY = 35, kTapRecRes = 40;
 
 // Plan-time per-(N, p, q) operand set for one stage direction.
 struct OperandPlanes {

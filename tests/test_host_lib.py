@@ -144,3 +144,13 @@ def test_oracle_cone_matches_full_lines():
         assert np.array_equal(ox.lines_at(x, 96, 8, 12, k), full[:, k])
     y = ox.fft3_exact(x.reshape(1, 40, 96)[:, :32, :], ((1, 1), (4, 8), (8, 12)))
     assert y.shape == (1, 32, 96)
+
+
+def test_axis_order_option_is_validated():
+    """The axis order must be a permutation of (0, 1, 2) (all zero = default)."""
+    from paper_2606_23698_amd import api
+    from paper_2606_23698_amd._lib import ObfftError
+    for order in ((0, 0, 1), (3, 1, 0), (-1, 1, 2), (1, 1, 1)):
+        with pytest.raises(ObfftError) as e:
+            api.Plan((32, 32, 32), axis_order=order)
+        assert e.value.status == 1, order
