@@ -2,8 +2,9 @@
 
 One step = one forward transform of the whole 1024^3 array (all six Bailey
 stage launches: three axes x two stages).  Input: uniform[-1, 1) real and
-imaginary parts from the seeded device generator (seed 2), resident in HBM
-before the timed region.  Prints one JSON line.
+imaginary parts from the PCG64 stream of seed 2 (all real parts, then all
+imaginary parts, C order), resident in HBM before the timed region.  Prints
+one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N]
                     [--substrate auto|fp8|int8] [--no-cpu]
@@ -69,9 +70,11 @@ def time_steps(fn, steps, warmup):
 
 
 def stage_durations(plan, x, y, ws_a, reps):
-    """Average duration of the fused stage kernel over the six launches of a transform."""
+    """Durations of the six stage launches of a transform (the same kernels
+    forward runs, launched through the stage entry point), with events between
+    consecutive launches on the launch stream and one synchronisation at the end."""
     import torch
-    durs = []
+    evs = []
     for _ in range(reps):
         cur = x
         for axis in (2, 1, 0):
@@ -80,15 +83,33 @@ def stage_durations(plan, x, y, ws_a, reps):
                 e0.record()
                 plan.stage(axis, stage, src, dst)
                 e1.record()
-                torch.cuda.synchronize()
-                durs.append(e0.elapsed_time(e1))
+                evs.append((e0, e1))
             cur = y
-    return sum(durs) / len(durs), durs
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in evs[-6:]]
 
 
-def precision_sweep(api, x, y_ref, steps):
+def sampled_line_errors(x_host, outs, samples):
+    """Normwise relative error of each output against the double-double DFT on
+    sampled final-axis lines (the oracle evaluates each line's cost cone)."""
+    from oracle import exact as ox
+    t0 = time.perf_counter()
+    ref = ox.dd_cone_lines(x_host, samples)
+    res = {}
+    for name, got in outs.items():
+        num = den = 0.0
+        for s, (hi, lo) in ref.items():
+            d = (np.asarray(got[s], dtype=np.complex128) - hi) - lo
+            num += float(np.sum(np.abs(d) ** 2))
+            den += float(np.sum(np.abs(hi) ** 2))
+        res[name] = math.sqrt(num / den)
+    res["oracle_s"] = round(time.perf_counter() - t0, 1)
+    return res
+
+
+def precision_sweep(api, x, y_ref, steps, samples=(), lines_out=None):
     """The other substrates and the H0 fold reduction (bit-identical outputs) and
-    the FP32 target at the same size."""
+    the FP32 target at the same size (its sampled lines go to lines_out)."""
     import torch
     out = {}
     for sub in ("fp8", "int8"):
@@ -113,10 +134,11 @@ def precision_sweep(api, x, y_ref, steps):
     plan = api.Plan(tuple(x.shape), precision="fp32")
     y32 = torch.empty_like(x32)
     ms, _ = time_steps(lambda: plan.forward(x32, y32), steps, 1)
-    err = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y_ref) / torch.linalg.vector_norm(y_ref))
-    out["fp32_target"] = {"ms": round(ms, 3), "rel_l2_vs_fp64": err,
+    if lines_out is not None:
+        lines_out.update({s: y32[:, s[0], s[1]].cpu().numpy() for s in samples})
+    out["fp32_target"] = {"ms": round(ms, 3),
                           "hbm_roof_ms": round(48.0 * x.numel() / (HBM_PEAK_GBS * 1e9) * 1e3, 3)}
-    print(f"[bench] fp32 target: {ms:.2f} ms, rel err vs FP64 {err:.2e}", file=sys.stderr, flush=True)
+    print(f"[bench] fp32 target: {ms:.2f} ms", file=sys.stderr, flush=True)
     del x32, y32, plan
     torch.cuda.empty_cache()
     return out
@@ -126,8 +148,7 @@ def batch_throughput(api, inputs, steps):
     """64 uneven transforms: one persistent launch per Bailey pass under a
     hipGraph, against a loop of single-transform plans."""
     import torch
-    shapes, _ = inputs.batch_shapes(3, 64)
-    xs = [inputs.device_uniform(s, 3 + i) for i, s in enumerate(shapes)]
+    shapes, xs = inputs.batch_to_device(3, 64)
     ys = [torch.empty_like(x) for x in xs]
     bp = api.BatchPlan(shapes)
     ms_b, _ = time_steps(lambda: bp.forward(xs, ys), steps, 1)
@@ -143,8 +164,8 @@ def batch_throughput(api, inputs, steps):
     print(f"[bench] batch64: {ms_b:.2f} ms graph vs {ms_l:.2f} ms loop", file=sys.stderr, flush=True)
     return {"transforms": len(shapes), "elements": elems, "ms": round(ms_b, 3), "loop_ms": round(ms_l, 3),
             "speedup_vs_loop": round(ms_l / ms_b, 3), "bit_identical_to_loop": same,
-            "workload": "64 complex FP64 3-D FFTs, extents from {64,96,128,192,256} per axis (seed 3), "
-                        "uniform[-1,1)"}
+            "workload": "64 complex FP64 3-D FFTs, extents from {64,96,128,192,256} per axis, "
+                        "uniform[-1,1) (PCG64 seed 3: shapes, then each member's data)"}
 
 
 def crt_methods(api, inputs, steps):
@@ -240,7 +261,7 @@ def cpu_baseline(N, pq, target_s=12.0):
     from oracle import exact as ox
     from paper_2606_23698_amd import inputs
     p, q = pq
-    threads = ox.default_threads()
+    threads = len(os.sched_getaffinity(0))
     nl = max(1, min(32768, (1 << 25) // N))
     x = inputs.uniform((nl, N), 2).reshape(nl, N)
     done, t0 = 0, time.perf_counter()
@@ -253,7 +274,7 @@ def cpu_baseline(N, pq, target_s=12.0):
     total_lines = 3 * N * N
     ms = dt * 1e3 * total_lines / done
     return {"value": round(ms, 1), "unit": "ms per transform (extrapolated)", "cores": threads,
-            "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
             "sample": f"{done} length-{N} line passes (both Bailey stages, exact int128 pipeline) "
                       f"in {dt:.1f} s, scaled x{total_lines / done:.2f} to the 3 N^2 line passes of "
                       f"one {N}^3 transform"}
@@ -275,6 +296,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-transform batched measurement")
     ap.add_argument("--no-crt", action="store_true", help="skip the reconstruction-method comparison")
     ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU share of the 8-GPU slab decomposition")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the error against the double-double oracle on sampled lines")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of the input (a known-size reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -292,7 +315,7 @@ def main():
     shape = (N, N, N)
     plan = api.Plan(shape, substrate=args.substrate, reduction=args.reduction)
     info = plan.info()
-    x = inputs.device_uniform(shape, 2, device=dev)
+    x = inputs.uniform_to_device(shape, 2, device=dev)
     y = torch.empty_like(x)
     print(f"[bench] {N}^3 plan ready: p={info['p']} q={info['q']} substrate={info['substrate']}",
           file=sys.stderr, flush=True)
@@ -303,18 +326,25 @@ def main():
         xc = x.clone()
         torch.cuda.synchronize()
         del xc
+    # sampled output lines (k2, k3) of the final axis for the accuracy check
+    samples = [(k2 % N, 5 % N) for k2 in (0, 17, 511, 1023, 256, 900)]
+    got = {"emulated": {s: y[:, s[0], s[1]].cpu().numpy() for s in samples}}
     ms_nat, diff = float("nan"), float("nan")
     if not args.no_native:
         yn = torch.empty_like(x)
         ms_nat, _ = time_steps(lambda: plan.native_forward(x, yn), args.steps, args.warmup)
         print(f"[bench] native forward: {ms_nat:.3f} ms/step", file=sys.stderr, flush=True)
         diff = float(torch.linalg.vector_norm(y - yn) / torch.linalg.vector_norm(yn))
+        got["native_fp64"] = {s: yn[:, s[0], s[1]].cpu().numpy() for s in samples}
         del yn
 
+    # the average launch of the dominant kernel over the timed region: the six
+    # stage launches are the whole step
     stage_ms = ms / 6.0
+    durs = []
     if args.stage_reps > 0:
         ws_a = torch.empty_like(x)
-        stage_ms, durs = stage_durations(plan, x, y, ws_a, args.stage_reps)
+        durs = stage_durations(plan, x, y, ws_a, args.stage_reps)
         print("[bench] stage launches (ms): " + " ".join(f"{d:.2f}" for d in durs), file=sys.stderr, flush=True)
         del ws_a
     torch.cuda.synchronize()
@@ -326,6 +356,8 @@ def main():
     copy_roof_ms = 96.0 * elems / (copy_gbs * 1e9) * 1e3
     n_out_launch = 2 * elems
     achieved = C_EPI_MIN * n_out_launch / (stage_ms * 1e-3) / 1e12
+    traffic = measured_traffic(N, info["substrate"]) if args.reduction == "reciprocal" else None
+    alg_bytes_launch = 16 * elems      # 96 B per element per transform over six launches
     line = {
         "metric": METRIC,
         "value": round(ms, 3),
@@ -339,7 +371,7 @@ def main():
         "vs_baseline": None,
         "dtype": SUB_DTYPE[info["substrate"]],
         "data": "synthetic",
-        "config": {"workload": f"forward complex FP64 3-D FFT {N}x{N}x{N}, Re/Im uniform[-1,1) seed 2",
+        "config": {"workload": f"forward complex FP64 3-D FFT {N}x{N}x{N}, Re/Im uniform[-1,1) (PCG64 seed 2)",
                    "n": shape, "p": info["p"], "q": info["q"], "moduli": info["r"],
                    "substrate": SUB_NAME[info["substrate"]], "reduction": args.reduction},
         "native_fp64_ms": round(ms_nat, 3) if ms_nat == ms_nat else None,
@@ -355,12 +387,38 @@ def main():
         "wall_ms_per_step": round(wall, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": measured_traffic(N, info["substrate"]) if args.reduction == "reciprocal" else None,
+                     "traffic": traffic,
                      "kernel": "ob_stage_kernel", "avg_launch_ms": round(stage_ms, 3),
-                     "algorithmic_per_launch": f"{C_EPI_MIN} integer ops x {n_out_launch} outputs"},
+                     "avg_launch_source": "ms_per_step / 6 (the six stage launches are the timed step)",
+                     "algorithmic_per_launch": f"{C_EPI_MIN} integer ops x {n_out_launch} outputs",
+                     "stage_launch_ms": [round(d, 3) for d in durs],
+                     "hbm_view": {"algorithmic_bytes_per_launch": alg_bytes_launch,
+                                  "achieved_GBs": round(alg_bytes_launch / (stage_ms * 1e-3) / 1e9, 1),
+                                  "peak_GBs": HBM_PEAK_GBS,
+                                  "frac": round(alg_bytes_launch / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "traffic_over_algorithmic": round(traffic / alg_bytes_launch, 3) if traffic else None}},
     }
+    lines32 = {}
     if not args.no_sweep:
-        line["precision_sweep"] = precision_sweep(api, x, y, max(2, min(args.steps, 3)))
+        line["precision_sweep"] = precision_sweep(api, x, y, max(2, min(args.steps, 3)), samples, lines32)
+    if not args.no_accuracy:
+        x_host = x.cpu().numpy()
+        err = sampled_line_errors(x_host, got, samples)
+        acc = {"rel_l2_emulated": err["emulated"], "rel_l2_native_fp64": err.get("native_fp64"),
+               "emulated_within_1e-14": bool(err["emulated"] <= 1e-14),
+               "lines": f"{len(samples)} sampled final-axis lines (k2, k3) = {samples}; the FP8 and INT8 "
+                        "substrates give the default's bits (precision_sweep), hence its error",
+               "oracle_s": err["oracle_s"]}
+        if lines32:
+            e32 = sampled_line_errors(x_host.astype(np.complex64), {"fp32": lines32}, samples)
+            acc["rel_l2_fp32_target"] = e32["fp32"]
+            acc["fp32_reference"] = "double-double DFT of the binary32-rounded input"
+            acc["oracle_s"] += e32["oracle_s"]
+        del x_host
+        line["accuracy_vs_double_double"] = acc
+        print(f"[bench] error vs double-double on {len(samples)} lines: emulated {err['emulated']:.3e}, "
+              f"native {err.get('native_fp64', float('nan')):.3e}, fp32 target "
+              f"{acc.get('rel_l2_fp32_target', float('nan')):.3e}", file=sys.stderr, flush=True)
     if not args.no_batch:
         del x, y
         torch.cuda.empty_cache()
