@@ -56,7 +56,10 @@ typedef enum {
   OBFFT_ALLOC_FAILED = 5,         /* device or host allocation failed */
   OBFFT_HIP_ERROR = 6,            /* a HIP runtime call failed */
   OBFFT_UNSUPPORTED_DEVICE = 7,   /* the current device is not gfx950 */
-  OBFFT_WRONG_PRECISION = 8       /* z2z call on an FP32 plan or c2c on an FP64 plan */
+  OBFFT_WRONG_PRECISION = 8,      /* z2z call on an FP32 plan or c2c on an FP64 plan */
+  OBFFT_BATCH_ABORTED = 9         /* a dependency wait of the persistent batched launch reached its
+                                     poll limit; every workgroup then left and the batch outputs are
+                                     incomplete (reported by obfft_last_error) */
 } obfft_status_t;
 
 /* Precision target.  FP64: r = 12 moduli (Sec. 2 shipping set), k = 53.
@@ -287,11 +290,13 @@ typedef struct {
 obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
 
 /* Batched transforms: `count` independent FP64 forward transforms of possibly
- * different shapes (host int64 [count][3]).  Each of the six Bailey passes
- * (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs as ONE launch over
- * the tiles of every member (one workgroup per tile, each finding its member
- * in a device descriptor table); the six launches are captured once
- * in a hipGraph and replayed.  Members with equal shapes share one plan.
+ * different shapes (host int64 [count][3]).  On the FP16 substrate the whole
+ * batch is one persistent launch (see obfft_batch_set_mode); otherwise each of
+ * the six Bailey passes (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs
+ * as one launch per contraction class over the tiles of every member (one
+ * workgroup per tile, each finding its member in a device descriptor table).
+ * The launches are captured once in a hipGraph and replayed.  Members with
+ * equal shapes share one plan.
  * Outputs are bit-identical to fft3d_z2z_forward on each member.  The batch
  * owns a workspace of the summed member sizes, allocated on first use.
  * 1 <= count <= 65535, else OBFFT_INVALID_VALUE.
@@ -300,8 +305,29 @@ obfft_status_t obfft_batch_plan_create(obfft_plan_t* plan, int count, const int6
                                        const obfft_options_t* opt);
 obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
                                    void* stream);
-/* use_graph = 0 launches the six passes directly instead of replaying the graph. */
+/* use_graph = 0 launches the batch directly instead of replaying the graph. */
 obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph);
+
+/* How a batch runs.
+ *   OBFFT_BATCH_PERSISTENT : one persistent launch over the tiles of every pass
+ *     of every member (FP16 substrate, the default there).  Workgroups (as many
+ *     as the device holds at once) claim tiles in pass-major order from a global
+ *     counter; a tile of pass s of a member waits until the member's pass s - 1
+ *     has completed every tile (per-(member, pass) counters with release and
+ *     acquire at device scope), so passes of different members overlap.  Each
+ *     wait polls at most the plan's poll limit (obfft_batch_set_poll_limit)
+ *     before the launch gives up: every workgroup then leaves, and
+ *     obfft_last_error reports OBFFT_BATCH_ABORTED.  A small clearing kernel
+ *     resets the counters before each launch; both are captured in the graph.
+ *   OBFFT_BATCH_PASSES : one launch per Bailey pass and contraction class (the
+ *     other substrates always run this way).
+ * Outputs are bit-identical in both modes.  OBFFT_INVALID_VALUE for a mode the
+ * plan cannot run. */
+enum { OBFFT_BATCH_PASSES = 0, OBFFT_BATCH_PERSISTENT = 1 };
+obfft_status_t obfft_batch_set_mode(obfft_plan_t plan, int mode);
+/* Polls of one dependency wait before the persistent launch gives up (default
+ * 2^24, several seconds; 0 gives up at the first unmet dependency). */
+obfft_status_t obfft_batch_set_poll_limit(obfft_plan_t plan, int polls);
 
 const char* obfft_status_string(obfft_status_t status);
 /* The status of the last failed call on this plan (OBFFT_SUCCESS if none),

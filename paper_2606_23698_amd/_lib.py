@@ -76,6 +76,8 @@ def lib():
         "obfft_batch_plan_create": (i32, [P(vp), i32, P(i64), P(Options)]),
         "obfft_batch_forward": (i32, [vp, P(vp), P(vp), vp]),
         "obfft_batch_set_graph": (i32, [vp, i32]),
+        "obfft_batch_set_mode": (i32, [vp, i32]),
+        "obfft_batch_set_poll_limit": (i32, [vp, i32]),
         "obfft_status_string": (ctypes.c_char_p, [i32]),
         "obfft_last_error": (i32, [vp]),
         "obfft_clear_error": (i32, [vp]),
@@ -106,5 +108,6 @@ EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", 
             "fft3d_z2z_native_forward", "fft3d_z2z_native_inverse", "obfft_stage", "obfft_debug_tap",
             "obfft_crt_reconstruct", "obfft_crt_reconstruct_method", "obfft_taps_layout", "obfft_mfma_probe",
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
-            "obfft_batch_forward", "obfft_batch_set_graph", "obfft_status_string", "obfft_last_error",
+            "obfft_batch_forward", "obfft_batch_set_graph", "obfft_batch_set_mode", "obfft_batch_set_poll_limit",
+            "obfft_status_string", "obfft_last_error",
             "obfft_clear_error"]

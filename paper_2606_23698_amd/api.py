@@ -206,8 +206,21 @@ class BatchPlan:
     def last_error(self):
         return int(L.lib().obfft_last_error(self._h))
 
+    def clear_error(self):
+        L.check(L.lib().obfft_clear_error(self._h), "obfft_clear_error")
+
     def set_graph(self, use_graph):
         L.check(L.lib().obfft_batch_set_graph(self._h, int(bool(use_graph))), "obfft_batch_set_graph")
+
+    BATCH_MODES = {"passes": 0, "persistent": 1}
+
+    def set_mode(self, mode):
+        """'persistent': one persistent launch over every pass (FP16 substrate);
+        'passes': one launch per Bailey pass and contraction class."""
+        L.check(L.lib().obfft_batch_set_mode(self._h, self.BATCH_MODES[mode]), "obfft_batch_set_mode")
+
+    def set_poll_limit(self, polls):
+        L.check(L.lib().obfft_batch_set_poll_limit(self._h, int(polls)), "obfft_batch_set_poll_limit")
 
     def forward(self, xs, outs=None, stream=None):
         if len(xs) != len(self.shapes):

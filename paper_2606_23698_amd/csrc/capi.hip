@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -28,6 +29,11 @@ hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, 
                         const uint16_t* tmember, int64_t total, hipStream_t st);
 int kclass_of(int K);
 int kclass_kmax(int c);
+int persist_lds_bytes(unsigned cls_mask);
+int persist_variant(int K);
+int persist_grid(int lds);
+hipError_t launch_persist(const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
+                          hipStream_t st);
 struct NativePlan;
 NativePlan* native_plan_create(const int64_t* n, std::string& err);
 void native_plan_destroy(NativePlan* np);
@@ -84,6 +90,16 @@ struct obfft_plan_s {
   hipStream_t capture_stream = nullptr;
   hipEvent_t desc_done = nullptr;     // the last descriptor upload has left the pinned buffer
   bool use_graph = true;
+  // persistent batched launch (FP16 substrate): one kernel over every pass
+  int batch_mode = OBFFT_BATCH_PASSES;
+  int persist_ok = 0;                 // the plan's substrate has the persistent kernel
+  int persist_nseg = 0, persist_grid_size = 0, persist_lds = 0, persist_spin = 1 << 24;
+  int64_t persist_items = 0;
+  PersistParams* d_persist = nullptr; // device copy of the kernel's parameter block
+  int64_t* d_seg_start = nullptr;
+  int* d_seg_dep = nullptr;
+  int* d_seg_cls = nullptr;
+  uint32_t* d_ctl = nullptr;          // [2 + nseg]: item counter, give-up flag, completed tiles
 };
 
 static obfft_status_t fail(obfft_plan_t plan, obfft_status_t s) {
@@ -318,6 +334,11 @@ extern "C" obfft_status_t obfft_plan_destroy(obfft_plan_t plan) {
   if (plan->d_tmember) (void)hipFree(plan->d_tmember);
   if (plan->h_desc) (void)hipHostFree(plan->h_desc);
   if (plan->batch_ws) (void)hipFree(plan->batch_ws);
+  if (plan->d_persist) (void)hipFree(plan->d_persist);
+  if (plan->d_seg_start) (void)hipFree(plan->d_seg_start);
+  if (plan->d_seg_dep) (void)hipFree(plan->d_seg_dep);
+  if (plan->d_seg_cls) (void)hipFree(plan->d_seg_cls);
+  if (plan->d_ctl) (void)hipFree(plan->d_ctl);
   for (void* d : plan->dev_allocs) hipFree(d);
   if (plan->ws_owned && plan->ws) hipFree(plan->ws);
   if (plan->native) native_plan_destroy(plan->native);
@@ -883,12 +904,68 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     return OBFFT_HIP_ERROR;
   }
   bp->members_of_batch = per;
+  // segments of the persistent launch: (pass, member) pass-major, each
+  // depending on the same member's previous pass
+  if (bp->substrate == SUB_FP16) {
+    const int nseg = 6 * count;
+    std::vector<int64_t> seg_start(nseg + 1, 0);
+    std::vector<int> seg_dep(nseg), seg_cls(nseg);
+    unsigned mask = 0;
+    for (int sg = 0; sg < nseg; sg++) {
+      seg_start[sg + 1] = seg_start[sg] + tiles[sg];
+      seg_dep[sg] = sg >= count ? sg - count : -1;
+      seg_cls[sg] = persist_variant(bp->h_desc[sg].K);
+      mask |= 1u << seg_cls[sg];
+    }
+    bp->persist_nseg = nseg;
+    bp->persist_items = seg_start[nseg];
+    bp->persist_lds = persist_lds_bytes(mask);
+    bp->persist_grid_size = persist_grid(bp->persist_lds);
+    if (bp->persist_grid_size <= 0 || seg_start[nseg] >= ((int64_t)1 << 32) - bp->persist_grid_size) {
+      obfft_plan_destroy(bp);
+      return OBFFT_HIP_ERROR;
+    }
+    if (hipMalloc((void**)&bp->d_seg_start, sizeof(int64_t) * (nseg + 1)) != hipSuccess ||
+        hipMalloc((void**)&bp->d_seg_dep, sizeof(int) * nseg) != hipSuccess ||
+        hipMalloc((void**)&bp->d_seg_cls, sizeof(int) * nseg) != hipSuccess ||
+        hipMalloc((void**)&bp->d_ctl, sizeof(uint32_t) * (2 + nseg)) != hipSuccess ||
+        hipMalloc((void**)&bp->d_persist, sizeof(PersistParams)) != hipSuccess) {
+      obfft_plan_destroy(bp);
+      return OBFFT_ALLOC_FAILED;
+    }
+    PersistParams Q;
+    memset(&Q, 0, sizeof(Q));
+    Q.descs = bp->d_desc;
+    Q.seg_start = bp->d_seg_start;
+    Q.seg_dep = bp->d_seg_dep;
+    Q.seg_cls = bp->d_seg_cls;
+    Q.nseg = nseg;
+    Q.spin_limit = bp->persist_spin;
+    Q.total = seg_start[nseg];
+    Q.ctl = bp->d_ctl;
+    Q.flags = bp->d_flags;
+    if (hipMemcpy(bp->d_seg_start, seg_start.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(bp->d_seg_dep, seg_dep.data(), sizeof(int) * nseg, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(bp->d_seg_cls, seg_cls.data(), sizeof(int) * nseg, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(bp->d_persist, &Q, sizeof(Q), hipMemcpyHostToDevice) != hipSuccess) {
+      obfft_plan_destroy(bp);
+      return OBFFT_HIP_ERROR;
+    }
+    bp->persist_ok = 1;
+    bp->batch_mode = OBFFT_BATCH_PERSISTENT;
+  }
   *out = bp;
   return OBFFT_SUCCESS;
 }
 
 static obfft_status_t batch_launch_passes(obfft_plan_t bp, hipStream_t st) {
   int count = bp->batch_count;
+  if (bp->batch_mode == OBFFT_BATCH_PERSISTENT)
+    return launch_persist(bp->d_persist, bp->d_ctl, 2 + bp->persist_nseg, bp->persist_grid_size, bp->persist_lds,
+                          st) == hipSuccess
+               ? OBFFT_SUCCESS
+               : OBFFT_HIP_ERROR;
   for (int pass = 0; pass < 6; pass++)
     for (int c = 0; c < 5; c++) {
       int64_t total = bp->batch_total[pass][c];
@@ -948,10 +1025,40 @@ extern "C" obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* con
   return OBFFT_SUCCESS;
 }
 
+static void drop_graph(obfft_plan_t plan) {
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  plan->graph_exec = nullptr;
+  plan->graph = nullptr;
+}
+
 // Selects graph replay (1, default) or direct launches (0) for a batch plan.
 extern "C" obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph) {
   if (!plan || !plan->batch_count) return OBFFT_INVALID_VALUE;
   plan->use_graph = use_graph != 0;
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_batch_set_mode(obfft_plan_t plan, int mode) {
+  if (!plan || !plan->batch_count) return OBFFT_INVALID_VALUE;
+  if (mode != OBFFT_BATCH_PASSES && mode != OBFFT_BATCH_PERSISTENT) return fail(plan, OBFFT_INVALID_VALUE);
+  if (mode == OBFFT_BATCH_PERSISTENT && !plan->persist_ok) return fail(plan, OBFFT_INVALID_VALUE);
+  if (mode != plan->batch_mode) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
+    drop_graph(plan);
+    plan->batch_mode = mode;
+  }
+  return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_batch_set_poll_limit(obfft_plan_t plan, int polls) {
+  if (!plan || !plan->batch_count || polls < 0) return OBFFT_INVALID_VALUE;
+  if (!plan->persist_ok) return fail(plan, OBFFT_INVALID_VALUE);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
+  plan->persist_spin = polls;
+  const size_t off = offsetof(PersistParams, spin_limit);
+  if (hipMemcpy((char*)plan->d_persist + off, &polls, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(plan, OBFFT_HIP_ERROR);
   return OBFFT_SUCCESS;
 }
 
@@ -995,6 +1102,7 @@ extern "C" const char* obfft_status_string(obfft_status_t s) {
     case OBFFT_HIP_ERROR: return "OBFFT_HIP_ERROR";
     case OBFFT_UNSUPPORTED_DEVICE: return "OBFFT_UNSUPPORTED_DEVICE";
     case OBFFT_WRONG_PRECISION: return "OBFFT_WRONG_PRECISION";
+    case OBFFT_BATCH_ABORTED: return "OBFFT_BATCH_ABORTED";
   }
   return "unknown status";
 }
@@ -1008,7 +1116,7 @@ extern "C" obfft_status_t obfft_last_error(obfft_plan_t plan) {
     if (f) {
       const uint32_t zero = 0;
       if (hipMemcpy(plan->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return OBFFT_HIP_ERROR;
-      plan->last = OBFFT_NONFINITE_INPUT;
+      plan->last = (f & 2u) ? OBFFT_BATCH_ABORTED : OBFFT_NONFINITE_INPUT;
     }
   }
   return plan->last;

@@ -1,5 +1,7 @@
 // Instantiations and host launchers of the Ozaki-Bailey stage kernels
 // (single transforms and the batched launches) for gfx950.
+#include <algorithm>
+
 #include "ob_stage.h"
 
 namespace obfft {
@@ -81,6 +83,163 @@ static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, 
       return F && full ? launch_batch_t<SUB, 32, F>(descs, first, tmember, total, st)
                        : launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
   }
+}
+
+// Persistent batched stage kernel (FP16 substrate, FP64 target): every
+// workgroup claims work items in order from a global counter until none are
+// left; an item is one tile of one (pass, member) segment.  Before a tile
+// whose segment depends on the member's previous pass, one thread polls that
+// pass's completion count with acquire semantics at agent scope (the tiles of
+// the previous pass were written by other workgroups, possibly on other
+// XCDs); after a tile, one thread adds 1 to its segment's count with release
+// semantics.  Items are claimed in increasing order and every dependency
+// points to smaller items, so the smallest unfinished item can always run:
+// the launch cannot deadlock, whatever the grid.  A wait that exceeds the
+// plan's poll limit raises the give-up flag, and every workgroup then leaves
+// at its next poll or claim, so the kernel always ends.
+__device__ __forceinline__ void persist_run_tile(int cls, const StageParams& P, int64_t c, int64_t g) {
+  switch (cls) {
+    case kPersistK4Packed: stage_tile<SUB_FP16, 0, 16, true, false, 4>(P, c, g); break;
+    case kPersistK8Packed: stage_tile<SUB_FP16, 0, 16, true, false, 2>(P, c, g); break;
+    case kPersistK12Full: stage_tile<SUB_FP16, 0, 12, true>(P, c, g); break;
+    case kPersistK12: stage_tile<SUB_FP16, 0, 12, false>(P, c, g); break;
+    case kPersistK16Full: stage_tile<SUB_FP16, 0, 16, true>(P, c, g); break;
+    case kPersistK16: stage_tile<SUB_FP16, 0, 16, false>(P, c, g); break;
+    case kPersistK32Full: stage_tile<SUB_FP16, 0, 32, true>(P, c, g); break;
+    default: stage_tile<SUB_FP16, 0, 32, false>(P, c, g); break;
+  }
+}
+
+// The parameters live in device memory and are re-read per item (scalar
+// loads) rather than held in registers across the tile body.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_persist_kernel(
+    const PersistParams* __restrict__ Qp) {
+  __shared__ int64_t s_item;
+  __shared__ int s_go, s_seg;
+  for (;;) {
+    const PersistParams* Qg = Qp;
+    asm volatile("" : "+s"(Qg));  // the parameter block is re-read after every tile
+    const OB_CONST PersistParams* Q = (const OB_CONST PersistParams*)Qg;  // scalar loads
+    OB_GLOBAL uint32_t* ctl = (OB_GLOBAL uint32_t*)Q->ctl;
+    const int64_t total = Q->total;
+    if (threadIdx.x == 0) {
+      const bool stop = __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      s_item = stop ? total : (int64_t)__hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= total) break;
+    // the segment of item `it`: the last d with seg_start[d] <= it
+    const OB_CONST int64_t* seg_start = (const OB_CONST int64_t*)Q->seg_start;
+    int lo = 0, hi = Q->nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (seg_start[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const int d = __builtin_amdgcn_readfirstlane(lo);
+    if (threadIdx.x == 0) {
+      int go = 1;
+      const int dep = ((const OB_CONST int*)Q->seg_dep)[d];
+      if (dep >= 0) {
+        const uint32_t need = (uint32_t)(seg_start[dep + 1] - seg_start[dep]);
+        const int limit = Q->spin_limit;
+        for (int k = 0;; k++) {
+          if (__hip_atomic_load(&ctl[2 + dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+          if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            go = 0;
+            break;
+          }
+          if (k >= limit) {
+            __hip_atomic_store(&ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or((OB_GLOBAL uint32_t*)Q->flags, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+      }
+      s_go = go;
+      s_seg = d;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    const int64_t local = it - seg_start[d];
+    const int cls = ((const OB_CONST int*)Q->seg_cls)[d];
+#if defined(__HIP_DEVICE_COMPILE__)
+    const StageParams P = ((const OB_CONST StageParams*)Q->descs)[d];  // scalar loads
+#else
+    const StageParams P = Q->descs[d];  // (host parse only)
+#endif
+    int64_t c, g;
+    decode_tile(P, local, c, g);
+    persist_run_tile(cls, P, c, g);
+    // every wave's stores are done (the barrier waits for them), then one
+    // release publishes the tile to the other workgroups
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      OB_GLOBAL uint32_t* ctl2 = (OB_GLOBAL uint32_t*)((const OB_CONST PersistParams*)Qp)->ctl;
+      __hip_atomic_fetch_add(&ctl2[2 + s_seg], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// LDS of the persistent kernel: the largest tile variant among `cls_mask`.
+int persist_lds_bytes(unsigned cls_mask) {
+  const int b[kPersistVariants] = {
+      stage_lds_bytes<SUB_FP16, 0, 16, 4>(16), stage_lds_bytes<SUB_FP16, 0, 16, 2>(16),
+      stage_lds_bytes<SUB_FP16, 0, 12, 1>(12), stage_lds_bytes<SUB_FP16, 0, 12, 1>(12),
+      stage_lds_bytes<SUB_FP16, 0, 16, 1>(16), stage_lds_bytes<SUB_FP16, 0, 16, 1>(16),
+      stage_lds_bytes<SUB_FP16, 0, 32, 1>(32), stage_lds_bytes<SUB_FP16, 0, 32, 1>(32)};
+  int m = 0;
+  for (int v = 0; v < kPersistVariants; v++)
+    if (cls_mask & (1u << v)) m = std::max(m, b[v]);
+  return m;
+}
+
+// Tile variant of a stage with contraction length K (the same choice as the
+// single-transform launch).
+int persist_variant(int K) {
+  if (K <= 4) return kPersistK4Packed;
+  if (K <= 8) return kPersistK8Packed;
+  if (K <= 12) return K == 12 ? kPersistK12Full : kPersistK12;
+  if (K <= 16) return K == 16 ? kPersistK16Full : kPersistK16;
+  return K == 32 ? kPersistK32Full : kPersistK32;
+}
+
+// Workgroups of the persistent launch: what the device holds at once.
+int persist_grid(int lds) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)ob_persist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024) != hipSuccess)
+      return -1;
+    attr_set = true;
+  }
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ob_persist_kernel, kThreads, lds) !=
+          hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  return std::max(1, per_cu) * std::max(1, cus);
+}
+
+// The control block is cleared by a kernel (not a memset), so that the pair
+// can be captured in a graph and replayed.
+hipError_t launch_persist(const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((ctl_words + 255) / 256)), dim3(256), 0, st, ctl, ctl_words);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ob_persist_kernel, dim3((unsigned)grid), dim3(kThreads), lds, st, Q);
+  return hipGetLastError();
 }
 
 // FP64-target batched launch over the members of one pass and K class.

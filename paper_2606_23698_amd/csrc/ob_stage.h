@@ -288,7 +288,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, 
   int* cexp = (int*)(col_out + NCR);
   int* pexp = cexp + NCR;
 
-  const int tid = threadIdx.x, lane = tid & 63;
+  // opaque to the optimiser: a persistent caller must not keep values derived
+  // from the thread index live across its loop (they are cheap to recompute)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile addressing stays scalar
   const int64_t cstart = ctile * NCR;
   if (tid < NCR) {

@@ -137,6 +137,33 @@ constexpr int kTapRecWords = 64;
 constexpr int kTapRecP = 0, kTapRecZ = 16, kTapRecW = 24, kTapRecZhat = 29, kTapRecR = 30,
               kTapRecExp = 34, kTapRecY = 35, kTapRecRes = 40;
 
+// The persistent batched launch: one kernel over the tiles of every Bailey
+// pass of every member.  Work items are numbered pass-major (all tiles of
+// pass 0 of every member, then pass 1, ...); a segment is the tiles of one
+// (pass, member), and a segment may start only when the same member's
+// previous pass (its dependency) has completed every tile.
+struct PersistParams {
+  const StageParams* descs;  // [nseg] stage of each segment (pass-major: pass * count + member)
+  const int64_t* seg_start;  // [nseg + 1] first item of each segment; seg_start[nseg] = total
+  const int* seg_dep;        // [nseg] the segment that must be complete first, or -1
+  const int* seg_cls;        // [nseg] tile variant (kPersist* below)
+  int nseg;
+  int spin_limit;            // polls of a dependency before the kernel gives up
+  int64_t total;             // items
+  uint32_t* ctl;             // [0] item counter, [1] give-up flag, [2 + seg] tiles completed
+  uint32_t* flags;           // the plan's status word: bit 1 = a dependency wait gave up
+};
+
+// Tile variants of the persistent kernel (FP16 substrate, FP64 target).
+enum {
+  kPersistK4Packed = 0,   // K <= 4: four columns per 16-row tile
+  kPersistK8Packed = 1,   // 4 < K <= 8: two columns per tile
+  kPersistK12Full = 2, kPersistK12 = 3,
+  kPersistK16Full = 4, kPersistK16 = 5,
+  kPersistK32Full = 6, kPersistK32 = 7,
+  kPersistVariants = 8
+};
+
 // Plan-time per-(N, p, q) operand set for one stage direction.
 struct OperandPlanes {
   uint8_t* dev;          // device copy

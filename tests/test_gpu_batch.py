@@ -1,10 +1,15 @@
-"""Batched uneven transforms: one persistent launch per Bailey pass, replayed from a hipGraph.
+"""Batched uneven transforms: one persistent launch over every Bailey pass of
+every member (or one launch per pass and contraction class), replayed from a
+hipGraph.
 
 Every member's output must be bit-identical to the single-transform path
-(the same plan, factorisation and axis order), on several graph replays with
-eager work and synchronisation in between, and with the graph switched off.
-At the full 64-transform workload, the smallest members are also checked
-against the oracle's exact pipeline.
+(the same plan, factorisation and axis order), in both modes, on several
+graph replays with eager work and synchronisation in between, and with the
+graph switched off.  At the full 64-transform workload, the smallest members
+are also checked against the oracle's exact pipeline.  The persistent
+launch's bounded dependency wait is exercised by a poll limit of zero set
+from the host: the kernel then gives up, every workgroup leaves, and the
+plan reports OBFFT_BATCH_ABORTED.
 """
 import numpy as np
 import pytest
@@ -15,13 +20,15 @@ from paper_2606_23698_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def test_batch_matches_single_transforms(gpu):
+@pytest.mark.parametrize("mode", ["persistent", "passes"])
+def test_batch_matches_single_transforms(gpu, mode):
     from paper_2606_23698_amd import api
     shapes, rng = inputs.batch_shapes(seed=3, count=64)
     shapes = [tuple(max(e // 4, 16) if e in (64, 128, 256) else e // 2 for e in s) for s in shapes[:10]]
     shapes += [(32, 64, 96), (64, 64, 64)]
     xs = [torch.from_numpy(inputs.uniform(s, 10 + i)).to(gpu) for i, s in enumerate(shapes)]
     bp = api.BatchPlan(shapes)
+    bp.set_mode(mode)
     ref = [api.get_plan(s).forward(x) for s, x in zip(shapes, xs)]
     torch.cuda.synchronize()
     for rep in range(3):
@@ -37,12 +44,15 @@ def test_batch_matches_single_transforms(gpu):
         assert torch.equal(o, r)
 
 
-def test_batch_on_the_two_m_tile_shape(gpu):
-    """A member with a length-32 contraction puts the whole batch on the K = 32 shape."""
+@pytest.mark.parametrize("mode", ["persistent", "passes"])
+def test_batch_on_the_two_m_tile_shape(gpu, mode):
+    """Members with length-32 contractions, ragged K (5, 9, 14, 20) and length-1
+    axes: every tile variant of the persistent launch."""
     from paper_2606_23698_amd import api
-    shapes = [(8, 16, 512), (16, 16, 16), (12, 8, 32), (4, 1024, 4)]
+    shapes = [(8, 16, 512), (16, 16, 16), (12, 8, 32), (4, 1024, 4), (25, 81, 196), (1, 45, 400), (3, 2, 7)]
     xs = [torch.from_numpy(inputs.uniform(s, 20 + i)).to(gpu) for i, s in enumerate(shapes)]
     bp = api.BatchPlan(shapes)
+    bp.set_mode(mode)
     ref = [api.get_plan(s).forward(x) for s, x in zip(shapes, xs)]
     outs = bp.forward(xs)
     torch.cuda.synchronize()
@@ -68,3 +78,25 @@ def test_batch_64_uneven_workload(gpu):
         pq = tuple(zip(plan.info()["p"], plan.info()["q"]))
         ref = ox.fft3_exact(xs[i].cpu().numpy(), pq)
         assert np.count_nonzero(outs[i].cpu().numpy() != ref) == 0, (i, shapes[i])
+
+
+def test_persistent_batch_gives_up_when_told(gpu):
+    """Poll limit 0: the first unmet dependency makes the persistent launch give
+    up; the kernel ends, the plan reports OBFFT_BATCH_ABORTED, and with the
+    limit restored the next call is complete and bit-exact again."""
+    from paper_2606_23698_amd import api
+    shapes = [(128, 128, 128), (64, 96, 64)]
+    xs = [torch.from_numpy(inputs.uniform(s, 40 + i)).to(gpu) for i, s in enumerate(shapes)]
+    ref = [api.get_plan(s).forward(x) for s, x in zip(shapes, xs)]
+    bp = api.BatchPlan(shapes)
+    bp.set_poll_limit(0)
+    bp.forward(xs)
+    torch.cuda.synchronize()
+    assert bp.last_error() == 9
+    bp.clear_error()
+    assert bp.last_error() == 0
+    bp.set_poll_limit(1 << 24)
+    outs = bp.forward(xs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
