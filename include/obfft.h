@@ -326,7 +326,7 @@ obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph);
 enum { OBFFT_BATCH_PASSES = 0, OBFFT_BATCH_PERSISTENT = 1 };
 obfft_status_t obfft_batch_set_mode(obfft_plan_t plan, int mode);
 /* Polls of one dependency wait before the persistent launch gives up (default
- * 2^24, several seconds; 0 gives up at the first unmet dependency). */
+ * 2^21, a few seconds; 0 gives up at the first unmet dependency). */
 obfft_status_t obfft_batch_set_poll_limit(obfft_plan_t plan, int polls);
 
 const char* obfft_status_string(obfft_status_t status);

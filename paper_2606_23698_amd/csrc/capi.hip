@@ -93,7 +93,7 @@ struct obfft_plan_s {
   // persistent batched launch (FP16 substrate): one kernel over every pass
   int batch_mode = OBFFT_BATCH_PASSES;
   int persist_ok = 0;                 // the plan's substrate has the persistent kernel
-  int persist_nseg = 0, persist_grid_size = 0, persist_lds = 0, persist_spin = 1 << 24;
+  int persist_nseg = 0, persist_grid_size = 0, persist_lds = 0, persist_spin = 1 << 21;
   int64_t persist_items = 0;
   PersistParams* d_persist = nullptr; // device copy of the kernel's parameter block
   int64_t* d_seg_start = nullptr;

@@ -112,10 +112,20 @@ __device__ __forceinline__ void persist_run_tile(int cls, const StageParams& P, 
 
 // The parameters live in device memory and are re-read per item (scalar
 // loads) rather than held in registers across the tile body.
+//
+// Ordering: every wave fences its own stores at agent scope (release) before
+// the end-of-tile barrier, because the barrier itself does not wait for
+// outstanding vector stores; thread 0 then publishes the tile with a release
+// add.  A waiter polls with relaxed loads and, once the dependency is
+// complete, every wave takes one acquire fence before the tile reads its
+// input.  A workgroup remembers the last dependency it has seen complete (it
+// stays complete for the rest of the launch), so consecutive tiles of one
+// segment poll and fence once.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_persist_kernel(
     const PersistParams* __restrict__ Qp) {
   __shared__ int64_t s_item;
-  __shared__ int s_go, s_seg;
+  __shared__ int s_go, s_seg, s_ready;
+  if (threadIdx.x == 0) s_ready = -1;
   for (;;) {
     const PersistParams* Qg = Qp;
     asm volatile("" : "+s"(Qg));  // the parameter block is re-read after every tile
@@ -140,13 +150,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
     const int d = __builtin_amdgcn_readfirstlane(lo);
     if (threadIdx.x == 0) {
-      int go = 1;
+      int go = 1;  // 0: leave, 1: run, 2: run after an acquire fence
       const int dep = ((const OB_CONST int*)Q->seg_dep)[d];
-      if (dep >= 0) {
+      if (dep >= 0 && dep != s_ready) {
         const uint32_t need = (uint32_t)(seg_start[dep + 1] - seg_start[dep]);
         const int limit = Q->spin_limit;
         for (int k = 0;; k++) {
-          if (__hip_atomic_load(&ctl[2 + dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+          if (__hip_atomic_load(&ctl[2 + dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+            go = 2;
+            s_ready = dep;
+            break;
+          }
           if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             go = 0;
             break;
@@ -164,7 +178,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       s_seg = d;
     }
     __syncthreads();
-    if (!s_go) break;
+    const int go = s_go;
+    if (!go) break;
+    if (go == 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int64_t local = it - seg_start[d];
     const int cls = ((const OB_CONST int*)Q->seg_cls)[d];
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -175,8 +191,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     int64_t c, g;
     decode_tile(P, local, c, g);
     persist_run_tile(cls, P, c, g);
-    // every wave's stores are done (the barrier waits for them), then one
-    // release publishes the tile to the other workgroups
+    // this wave's stores are complete and visible at agent scope before the
+    // barrier; then one release add publishes the tile
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
       OB_GLOBAL uint32_t* ctl2 = (OB_GLOBAL uint32_t*)((const OB_CONST PersistParams*)Qp)->ctl;

@@ -95,7 +95,7 @@ def test_persistent_batch_gives_up_when_told(gpu):
     assert bp.last_error() == 9
     bp.clear_error()
     assert bp.last_error() == 0
-    bp.set_poll_limit(1 << 24)
+    bp.set_poll_limit(1 << 21)
     outs = bp.forward(xs)
     torch.cuda.synchronize()
     for o, r in zip(outs, ref):
