@@ -26,7 +26,9 @@ _IP = ctypes.POINTER(ctypes.c_int)
 def lib():
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
+        # OBFFT_ORACLE_LIB: another build of the same sources (the host
+        # sanitizer test loads an instrumented one)
+        path = os.environ.get("OBFFT_ORACLE_LIB") or _build.ensure_built()
         L = ctypes.CDLL(path)
         L.oracle_fft3.restype = ctypes.c_int
         L.oracle_fft3.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _I64P, _I64P, _I64P, _IP,
