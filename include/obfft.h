@@ -57,9 +57,11 @@ typedef enum {
   OBFFT_HIP_ERROR = 6,            /* a HIP runtime call failed */
   OBFFT_UNSUPPORTED_DEVICE = 7,   /* the current device is not gfx950 */
   OBFFT_WRONG_PRECISION = 8,      /* z2z call on an FP32 plan or c2c on an FP64 plan */
-  OBFFT_BATCH_ABORTED = 9         /* a dependency wait of the persistent batched launch reached its
+  OBFFT_BATCH_ABORTED = 9,        /* a dependency wait of the persistent batched launch reached its
                                      poll limit; every workgroup then left and the batch outputs are
                                      incomplete (reported by obfft_last_error) */
+  OBFFT_SCRATCH_EXCEEDED = 10     /* the allocation-free entry point was called on a plan whose
+                                     workspace exceeds the library's fixed scratch array */
 } obfft_status_t;
 
 /* Precision target.  FP64: r = 12 moduli (Sec. 2 shipping set), k = 53.
@@ -160,6 +162,23 @@ obfft_status_t obfft_plan_roots(obfft_plan_t plan, int axis, int64_t* host_out);
 obfft_status_t fft3d_z2z_forward(obfft_plan_t plan, const void* in, void* out, void* stream);
 obfft_status_t fft3d_z2z_inverse(obfft_plan_t plan, const void* in, void* out, void* stream);
 obfft_status_t fft3d_z2z_adjoint(obfft_plan_t plan, const void* in, void* out, void* stream);
+
+/* Forward transform that allocates nothing, for callers that cannot
+ * allocate device memory (code under stream or graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same result, bit for bit, as
+ * fft3d_z2z_forward on the same plan.  The Y' workspace is a fixed device
+ * array inside the library (obfft_noalloc_scratch_bytes() bytes, 256 MiB:
+ * every transform of at most 2^24 complex128 elements, e.g. 256^3); each
+ * device that loads the library holds its own copy until the process ends.
+ * A plan whose workspace_bytes exceeds it is rejected with
+ * OBFFT_SCRATCH_EXCEEDED before anything is launched.  The call does not
+ * allocate: no hipMalloc/hipFree, and the plan's own workspace is neither
+ * used nor created.  Every call on one device shares that device's array
+ * (its contents are not carried between calls), so calls that overlap in
+ * time on one device -- on different streams, or from different threads
+ * -- race and must be serialised by the caller. */
+obfft_status_t fft3d_z2z_forward_noalloc(obfft_plan_t plan, const void* in, void* out, void* stream);
+size_t obfft_noalloc_scratch_bytes(void);
 
 /* FP32-target transforms (complex64 in/out) on a plan made with
  * precision = OBFFT_PREC_FP32 (Sec. 7). */

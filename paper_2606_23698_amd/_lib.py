@@ -59,6 +59,8 @@ def lib():
         "obfft_set_workspace": (i32, [vp, vp, ctypes.c_size_t]),
         "obfft_plan_roots": (i32, [vp, i32, P(i64)]),
         "fft3d_z2z_forward": (i32, [vp, vp, vp, vp]),
+        "fft3d_z2z_forward_noalloc": (i32, [vp, vp, vp, vp]),
+        "obfft_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "fft3d_z2z_inverse": (i32, [vp, vp, vp, vp]),
         "fft3d_z2z_adjoint": (i32, [vp, vp, vp, vp]),
         "fft3d_c2c_forward": (i32, [vp, vp, vp, vp]),
@@ -110,4 +112,4 @@ EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", 
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
             "obfft_batch_forward", "obfft_batch_set_graph", "obfft_batch_set_mode", "obfft_batch_set_poll_limit",
             "obfft_status_string", "obfft_last_error",
-            "obfft_clear_error"]
+            "obfft_clear_error", "fft3d_z2z_forward_noalloc", "obfft_noalloc_scratch_bytes"]

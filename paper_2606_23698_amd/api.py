@@ -135,6 +135,14 @@ class Plan:
         return self._run("fft3d_z2z_forward" if self.precision == "fp64" else "fft3d_c2c_forward",
                          x, out, stream)
 
+    def forward_noalloc(self, x, out, stream=None):
+        """Forward transform through the allocation-free entry point (FP64
+        plans): the library's fixed scratch array replaces the plan's
+        workspace, and `out` must be supplied."""
+        if out is None:
+            raise ValueError("forward_noalloc writes into a caller-supplied output")
+        return self._run("fft3d_z2z_forward_noalloc", x, out, stream)
+
     def inverse(self, x, out=None, stream=None):
         return self._run("fft3d_z2z_inverse" if self.precision == "fp64" else "fft3d_c2c_inverse",
                          x, out, stream)

@@ -525,14 +525,20 @@ static obfft_status_t run_stage(obfft_plan_t plan, int axis, int stage, int dire
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// ws: the Y' workspace to use instead of the plan's (null: the plan's,
+// allocated on first use).
 static obfft_status_t run_transform(obfft_plan_t plan, const void* in, void* out, int direction,
-                                    bool normalise, void* stream) {
+                                    bool normalise, void* stream, void* ws = nullptr) {
   if (!in || !out) return OBFFT_INVALID_VALUE;
   int64_t total = plan->n[0] * plan->n[1] * plan->n[2];
   size_t bytes = (size_t)total * (plan->precision ? 8 : 16);
   if (overlaps(in, out, bytes)) return OBFFT_INVALID_VALUE;
-  obfft_status_t s = ensure_ws(plan);
-  if (s != OBFFT_SUCCESS) return s;
+  obfft_status_t s = OBFFT_SUCCESS;
+  if (!ws) {
+    s = ensure_ws(plan);
+    if (s != OBFFT_SUCCESS) return s;
+    ws = plan->ws;
+  }
   hipStream_t st = (hipStream_t)stream;
   int shift = 0;
   bool post_scale = false;
@@ -548,9 +554,9 @@ static obfft_status_t run_transform(obfft_plan_t plan, const void* in, void* out
   const void* cur = in;
   for (int k = 0; k < 3; k++) {
     int a = plan->order[k];
-    s = run_stage(plan, a, 1, direction, cur, plan->ws, 0, nullptr, st);
+    s = run_stage(plan, a, 1, direction, cur, ws, 0, nullptr, st);
     if (s != OBFFT_SUCCESS) return s;
-    s = run_stage(plan, a, 2, direction, plan->ws, out, k == 2 ? shift : 0, nullptr, st);
+    s = run_stage(plan, a, 2, direction, ws, out, k == 2 ? shift : 0, nullptr, st);
     if (s != OBFFT_SUCCESS) return s;
     cur = out;
   }
@@ -570,6 +576,47 @@ extern "C" obfft_status_t fft3d_z2z_forward(obfft_plan_t plan, const void* in, v
   CHECK_PLAN(OBFFT_PREC_FP64);
   return fail(plan, run_transform(plan, in, out, 0, false, stream));
 }
+// ---- forward transform without any allocation ----
+//
+// The Y' workspace between the two stages of each axis lives in a file-scope
+// device array.  Each device that runs the library holds its own copy (at
+// its own address) from module load until the process ends; host code uses
+// only the address hipGetSymbolAddress returns for the current device, never
+// the array's name, which on the host is a stand-in and not a device address.
+// Every call on one device shares that device's array; the workspace is
+// written in full by stage 1 before stage 2 reads it, so nothing has to be
+// cleared between calls, but calls that overlap in time on one device race.
+static constexpr size_t kScratchBytes = (size_t)256 << 20;  // 2^24 complex128 elements, e.g. 256^3
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices];
+
+static obfft_status_t scratch_for_current_device(void** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OBFFT_HIP_ERROR;
+  if (dev < 0 || dev >= kScratchDevices) return OBFFT_UNSUPPORTED_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OBFFT_HIP_ERROR;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return OBFFT_SUCCESS;
+}
+
+extern "C" size_t obfft_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" obfft_status_t fft3d_z2z_forward_noalloc(obfft_plan_t plan, const void* in, void* out, void* stream) {
+  CHECK_PLAN(OBFFT_PREC_FP64);
+  if (plan->ws_bytes > kScratchBytes) return fail(plan, OBFFT_SCRATCH_EXCEEDED);
+  void* ws = nullptr;
+  const obfft_status_t s = scratch_for_current_device(&ws);
+  if (s != OBFFT_SUCCESS) return fail(plan, s);
+  return fail(plan, run_transform(plan, in, out, 0, false, stream, ws));
+}
+
 extern "C" obfft_status_t fft3d_z2z_inverse(obfft_plan_t plan, const void* in, void* out, void* stream) {
   CHECK_PLAN(OBFFT_PREC_FP64);
   return fail(plan, run_transform(plan, in, out, 1, true, stream));
@@ -1103,6 +1150,7 @@ extern "C" const char* obfft_status_string(obfft_status_t s) {
     case OBFFT_UNSUPPORTED_DEVICE: return "OBFFT_UNSUPPORTED_DEVICE";
     case OBFFT_WRONG_PRECISION: return "OBFFT_WRONG_PRECISION";
     case OBFFT_BATCH_ABORTED: return "OBFFT_BATCH_ABORTED";
+    case OBFFT_SCRATCH_EXCEEDED: return "OBFFT_SCRATCH_EXCEEDED";
   }
   return "unknown status";
 }
