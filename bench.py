@@ -145,13 +145,20 @@ def precision_sweep(api, x, y_ref, steps, samples=(), lines_out=None):
 
 
 def batch_throughput(api, inputs, steps):
-    """64 uneven transforms: one persistent launch per Bailey pass under a
-    hipGraph, against a loop of single-transform plans."""
+    """64 uneven transforms under a hipGraph: one launch per Bailey pass and
+    contraction class (the default), one persistent launch over every pass,
+    and the same with the autotuner's factorisation per member shape, against
+    loops of single-transform plans."""
     import torch
+    from paper_2606_23698_amd import autotune
     shapes, xs = inputs.batch_to_device(3, 64)
     ys = [torch.empty_like(x) for x in xs]
     bp = api.BatchPlan(shapes)
     ms_b, _ = time_steps(lambda: bp.forward(xs, ys), steps, 1)
+    bp.set_mode("persistent")
+    ysp = [torch.empty_like(x) for x in xs]
+    ms_p, _ = time_steps(lambda: bp.forward(xs, ysp), steps, 1)
+    claim = bp.claim()
     plans = [api.get_plan(s) for s in shapes]
     ys2 = [torch.empty_like(x) for x in xs]
 
@@ -160,10 +167,35 @@ def batch_throughput(api, inputs, steps):
             pl.forward(x, o)
     ms_l, _ = time_steps(loop, steps, 1)
     same = all(torch.equal(torch.view_as_real(a), torch.view_as_real(b)) for a, b in zip(ys, ys2))
+    same_p = all(torch.equal(torch.view_as_real(a), torch.view_as_real(b)) for a, b in zip(ysp, ys2))
+    del ysp, bp
+    # per-member tuned options (factorisation and tile order per distinct shape)
+    t0 = time.perf_counter()
+    mo = autotune.tune_batch(shapes, reps=2)
+    tune_s = time.perf_counter() - t0
+    bt = api.BatchPlan(shapes, substrate="fp16", member_options=mo)
+    ms_t, _ = time_steps(lambda: bt.forward(xs, ys), steps, 1)
+    tplans = {}
+    for s, m in zip(shapes, mo):
+        key = (s, tuple(m["pq"]), m["group_block"])
+        if key not in tplans:
+            tplans[key] = api.Plan(s, substrate="fp16", pq=m["pq"], group_block=m["group_block"])
+
+    def tloop():
+        for s, m, x, o in zip(shapes, mo, xs, ys2):
+            tplans[(s, tuple(m["pq"]), m["group_block"])].forward(x, o)
+    ms_tl, _ = time_steps(tloop, steps, 1)
+    same_t = all(torch.equal(torch.view_as_real(a), torch.view_as_real(b)) for a, b in zip(ys, ys2))
     elems = sum(int(np.prod(s)) for s in shapes)
-    print(f"[bench] batch64: {ms_b:.2f} ms graph vs {ms_l:.2f} ms loop", file=sys.stderr, flush=True)
+    print(f"[bench] batch64: {ms_b:.2f} ms per-pass graph, {ms_p:.2f} ms persistent (claim {claim}), "
+          f"{ms_l:.2f} ms loop; tuned {ms_t:.2f} ms vs tuned loop {ms_tl:.2f} ms", file=sys.stderr, flush=True)
     return {"transforms": len(shapes), "elements": elems, "ms": round(ms_b, 3), "loop_ms": round(ms_l, 3),
             "speedup_vs_loop": round(ms_l / ms_b, 3), "bit_identical_to_loop": same,
+            "persistent_ms": round(ms_p, 3), "persistent_claim": claim,
+            "persistent_bit_identical_to_loop": same_p,
+            "tuned": {"ms": round(ms_t, 3), "loop_ms": round(ms_tl, 3), "speedup_vs_loop": round(ms_tl / ms_t, 3),
+                      "bit_identical_to_tuned_loop": same_t, "tune_s": round(tune_s, 1),
+                      "distinct_shapes": len({tuple(s) for s in shapes})},
             "workload": "64 complex FP64 3-D FFTs, extents from {64,96,128,192,256} per axis, "
                         "uniform[-1,1) (PCG64 seed 3: shapes, then each member's data)"}
 

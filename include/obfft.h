@@ -203,7 +203,10 @@ obfft_status_t fft3d_z2z_native_inverse(obfft_plan_t plan, const void* in, void*
  * record of output slot t (the slot order of the stage, as obfft_stage) is:
  *   [0, S)      Phase-A slice sums P_s (int32, Eq. slicing)
  *   [16, 16+T)  Phase-A lift sums Z_t (int32, Sec. 5.1)
- *   [24, 29)    E = sum_s 256^s P_s, two's complement, little-endian words
+ *   [24, 29)    E = sum_s 256^s P_s modulo 2^(32 w), little-endian words, w = 4
+ *               (FP64 target) or 3 (FP32), higher words zero: the kernel's
+ *               Kulisch accumulator keeps only these low bits of E (|E| may
+ *               reach 2^131), all that R = E - zhat M (|R| < 2^113) needs
  *   29          zhat = round-half-up(2^-48 sum_t 256^t Z_t) (int32)
  *   [30, 34)    R = E - zhat M, the exact stage integer (two's complement)
  *   34          the pack exponent: the output is RNE(R 2^exp) (int32)
@@ -309,12 +312,13 @@ typedef struct {
 obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
 
 /* Batched transforms: `count` independent FP64 forward transforms of possibly
- * different shapes (host int64 [count][3]).  On the FP16 substrate the whole
- * batch is one persistent launch (see obfft_batch_set_mode); otherwise each of
- * the six Bailey passes (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs
- * as one launch per contraction class over the tiles of every member (one
- * workgroup per tile, each finding its member in a device descriptor table).
- * The launches are captured once in a hipGraph and replayed.  Members with
+ * different shapes (host int64 [count][3]).  By default each of the six Bailey
+ * passes (axis n3 stage 1, n3 stage 2, n2 ..., n1 stage 2) runs as one launch
+ * per contraction class over the tiles of every member (one workgroup per
+ * tile, each finding its member in a device descriptor table); on the FP16
+ * substrate the whole batch may instead run as one persistent launch
+ * (obfft_batch_set_mode).  The launches are captured once in a hipGraph and
+ * replayed.  Members with
  * equal shapes share one plan.
  * Outputs are bit-identical to fft3d_z2z_forward on each member.  The batch
  * owns a workspace of the summed member sizes, allocated on first use.
@@ -322,6 +326,15 @@ obfft_status_t obfft_crt_constants(int precision, obfft_crt_constants_t* out);
  * ins/outs: host arrays of `count` device pointers. */
 obfft_status_t obfft_batch_plan_create(obfft_plan_t* plan, int count, const int64_t* shapes,
                                        const obfft_options_t* opt);
+/* The same with options per member (host array of `count`): each member may
+ * take its own factorisation, axis order and tile order (an autotuner's
+ * choice per shape; the tile variant of every stage follows from its
+ * contraction length).  Every member's output is bit-identical to
+ * fft3d_z2z_forward on a plan made with that member's options.  All members
+ * must share precision (FP64), substrate and reduction, and take no modulus
+ * override, else OBFFT_INVALID_VALUE. */
+obfft_status_t obfft_batch_plan_create_each(obfft_plan_t* plan, int count, const int64_t* shapes,
+                                            const obfft_options_t* opts);
 obfft_status_t obfft_batch_forward(obfft_plan_t plan, const void* const* ins, void* const* outs,
                                    void* stream);
 /* use_graph = 0 launches the batch directly instead of replaying the graph. */
@@ -329,17 +342,20 @@ obfft_status_t obfft_batch_set_graph(obfft_plan_t plan, int use_graph);
 
 /* How a batch runs.
  *   OBFFT_BATCH_PERSISTENT : one persistent launch over the tiles of every pass
- *     of every member (FP16 substrate, the default there).  Workgroups (as many
- *     as the device holds at once) claim tiles in pass-major order from a global
- *     counter; a tile of pass s of a member waits until the member's pass s - 1
- *     has completed every tile (per-(member, pass) counters with release and
- *     acquire at device scope), so passes of different members overlap.  Each
+ *     of every member (FP16 substrate).  Workgroups (as many as the device
+ *     holds at once) claim tiles in pass-major order from a global counter, a
+ *     few at a time (obfft_batch_set_claim); a tile of pass s of a member waits
+ *     until the member's pass s - 1 has completed every tile (per-(member,
+ *     pass) counters with release and acquire at device scope), so passes of
+ *     different members overlap.  On this 8-XCD part each release writes back
+ *     an XCD's L2 and each acquire invalidates it, which costs more than the
+ *     kernel boundaries of the per-pass launches, so it is not the default.  Each
  *     wait polls at most the plan's poll limit (obfft_batch_set_poll_limit)
  *     before the launch gives up: every workgroup then leaves, and
  *     obfft_last_error reports OBFFT_BATCH_ABORTED.  A small clearing kernel
  *     resets the counters before each launch; both are captured in the graph.
  *   OBFFT_BATCH_PASSES : one launch per Bailey pass and contraction class (the
- *     other substrates always run this way).
+ *     default; the other substrates always run this way).
  * Outputs are bit-identical in both modes.  OBFFT_INVALID_VALUE for a mode the
  * plan cannot run. */
 enum { OBFFT_BATCH_PASSES = 0, OBFFT_BATCH_PERSISTENT = 1 };
@@ -347,6 +363,16 @@ obfft_status_t obfft_batch_set_mode(obfft_plan_t plan, int mode);
 /* Polls of one dependency wait before the persistent launch gives up (default
  * 2^21, a few seconds; 0 gives up at the first unmet dependency). */
 obfft_status_t obfft_batch_set_poll_limit(obfft_plan_t plan, int polls);
+
+/* Items (tiles) a workgroup of the persistent launch claims at once, 1..256
+ * (else OBFFT_INVALID_VALUE).  A workgroup publishes the finished tiles of
+ * one segment together, and each publication makes its XCD write back its
+ * L2, so larger claims mean fewer write-backs and coarser load balance.
+ * The plan picks about four claims per workgroup over the batch, at most 64;
+ * obfft_batch_get_claim returns the current value (0 for a plan without a
+ * persistent launch).  Changes speed only, never results. */
+obfft_status_t obfft_batch_set_claim(obfft_plan_t plan, int items);
+int obfft_batch_get_claim(obfft_plan_t plan);
 
 const char* obfft_status_string(obfft_status_t status);
 /* The status of the last failed call on this plan (OBFFT_SUCCESS if none),

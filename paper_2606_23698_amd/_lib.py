@@ -76,10 +76,13 @@ def lib():
         "obfft_quantised_roots": (i32, [i64, i32, P(i64)]),
         "obfft_crt_constants": (i32, [i32, P(CrtConstants)]),
         "obfft_batch_plan_create": (i32, [P(vp), i32, P(i64), P(Options)]),
+        "obfft_batch_plan_create_each": (i32, [P(vp), i32, P(i64), P(Options)]),
         "obfft_batch_forward": (i32, [vp, P(vp), P(vp), vp]),
         "obfft_batch_set_graph": (i32, [vp, i32]),
         "obfft_batch_set_mode": (i32, [vp, i32]),
         "obfft_batch_set_poll_limit": (i32, [vp, i32]),
+        "obfft_batch_set_claim": (i32, [vp, i32]),
+        "obfft_batch_get_claim": (i32, [vp]),
         "obfft_status_string": (ctypes.c_char_p, [i32]),
         "obfft_last_error": (i32, [vp]),
         "obfft_clear_error": (i32, [vp]),
@@ -112,4 +115,5 @@ EXPORTED = ["obfft_options_default", "obfft_plan_create", "obfft_plan_destroy", 
             "obfft_quantised_roots", "obfft_crt_constants", "obfft_batch_plan_create",
             "obfft_batch_forward", "obfft_batch_set_graph", "obfft_batch_set_mode", "obfft_batch_set_poll_limit",
             "obfft_status_string", "obfft_last_error",
-            "obfft_clear_error", "fft3d_z2z_forward_noalloc", "obfft_noalloc_scratch_bytes"]
+            "obfft_clear_error", "fft3d_z2z_forward_noalloc", "obfft_noalloc_scratch_bytes",
+            "obfft_batch_plan_create_each", "obfft_batch_set_claim", "obfft_batch_get_claim"]

@@ -201,14 +201,27 @@ class Plan:
 class BatchPlan:
     """Several independent FP64 transforms of (possibly) different shapes."""
 
-    def __init__(self, shapes, substrate="auto"):
+    def __init__(self, shapes, substrate="auto", member_options=None):
+        """member_options: None (library defaults for every member) or one dict
+        per member with any of "pq", "group_block", "axis_order" (for example
+        an autotuner's choice per shape)."""
         self.shapes = [tuple(int(n) for n in s) for s in shapes]
         arr = np.ascontiguousarray(np.array(self.shapes, dtype=np.int64).reshape(-1))
-        opt, _ = options("fp64", substrate)
         h = ctypes.c_void_p()
-        L.check(L.lib().obfft_batch_plan_create(ctypes.byref(h), len(self.shapes),
-                                                arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                                ctypes.byref(opt)), "obfft_batch_plan_create")
+        shp = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        if member_options is None:
+            opt, _ = options("fp64", substrate)
+            L.check(L.lib().obfft_batch_plan_create(ctypes.byref(h), len(self.shapes), shp, ctypes.byref(opt)),
+                    "obfft_batch_plan_create")
+        else:
+            if len(member_options) != len(self.shapes):
+                raise ValueError("one options dict per member")
+            opts = (L.Options * len(self.shapes))()
+            for i, mo in enumerate(member_options):
+                opts[i], _ = options("fp64", substrate, pq=mo.get("pq"), group_block=mo.get("group_block", 0),
+                                     axis_order=mo.get("axis_order"))
+            L.check(L.lib().obfft_batch_plan_create_each(ctypes.byref(h), len(self.shapes), shp, opts),
+                    "obfft_batch_plan_create_each")
         self._h = h
 
     def last_error(self):
@@ -229,6 +242,13 @@ class BatchPlan:
 
     def set_poll_limit(self, polls):
         L.check(L.lib().obfft_batch_set_poll_limit(self._h, int(polls)), "obfft_batch_set_poll_limit")
+
+    def set_claim(self, items):
+        """Tiles a workgroup of the persistent launch claims at once (1..256)."""
+        L.check(L.lib().obfft_batch_set_claim(self._h, int(items)), "obfft_batch_set_claim")
+
+    def claim(self):
+        return int(L.lib().obfft_batch_get_claim(self._h))
 
     def forward(self, xs, outs=None, stream=None):
         if len(xs) != len(self.shapes):

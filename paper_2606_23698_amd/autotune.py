@@ -141,3 +141,23 @@ def tuned_plan(shape, precision="fp64", **kw):
     t = tune(shape, precision, **kw)
     return api.Plan(shape, precision=precision, substrate=t["substrate"], pq=[tuple(v) for v in t["pq"]],
                     group_block=t.get("group_block", 0))
+
+
+def tune_batch(shapes, reps=3, max_splits=2, use_cache=True):
+    """Per-member choices for a batched plan: every distinct shape is tuned on
+    the FP16 substrate (the persistent batch kernel's) over its factorisation
+    (which fixes the tile variant of each stage: the packed four- and
+    two-column tiles for K <= 4 and K <= 8, the full-length tiles at K = 12,
+    16 and 32, the general ones otherwise) and the stage-2 tile order.
+    Returns one options dict per member, for api.BatchPlan(member_options=...)."""
+    per_shape = {}
+    for s in shapes:
+        s = tuple(int(n) for n in s)
+        if s not in per_shape:
+            t = tune(s, substrates=("fp16",), reps=reps, max_splits=max_splits, use_cache=use_cache)
+            per_shape[s] = {"pq": [tuple(v) for v in t["pq"]], "group_block": t.get("group_block", 0)}
+    return [dict(per_shape[tuple(int(n) for n in s)]) for s in shapes]
+
+
+def tuned_batch_plan(shapes, **kw):
+    return api.BatchPlan(shapes, substrate="fp16", member_options=tune_batch(shapes, **kw))

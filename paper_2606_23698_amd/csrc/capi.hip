@@ -31,8 +31,8 @@ int kclass_of(int K);
 int kclass_kmax(int c);
 int persist_lds_bytes(unsigned cls_mask);
 int persist_variant(int K);
-int persist_grid(int lds);
-hipError_t launch_persist(const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
+int persist_grid(unsigned mask, int lds);
+hipError_t launch_persist(unsigned mask, const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
                           hipStream_t st);
 struct NativePlan;
 NativePlan* native_plan_create(const int64_t* n, std::string& err);
@@ -94,6 +94,8 @@ struct obfft_plan_s {
   int batch_mode = OBFFT_BATCH_PASSES;
   int persist_ok = 0;                 // the plan's substrate has the persistent kernel
   int persist_nseg = 0, persist_grid_size = 0, persist_lds = 0, persist_spin = 1 << 21;
+  int persist_claim = 1;              // items a workgroup claims at once
+  unsigned persist_mask = 0;          // tile variants the batch's stages need
   int64_t persist_items = 0;
   PersistParams* d_persist = nullptr; // device copy of the kernel's parameter block
   int64_t* d_seg_start = nullptr;
@@ -420,6 +422,7 @@ static void div_magic(int64_t d, uint32_t* magic, uint32_t* shift) {
 // Groups of one column tile run back to back on one XCD (stage 2 of the
 // contiguous axis): their partial output lines merge in that XCD's L2.
 static const int kGroupBlock = 8;
+static const int kMaxClaim = 256;   // items per claim of the persistent batched launch
 
 static dim3 stage_grid(StageParams& P, int64_t tiles) {
   const int64_t kMaxYZ = 65535;
@@ -708,15 +711,16 @@ extern "C" obfft_status_t obfft_debug_tap(obfft_plan_t plan, int axis, int stage
     memset(o, 0, kTapRecWords * sizeof(uint32_t));
     for (int q = 0; q < C.S; q++) o[kTapRecP + q] = t[kTapRecP + q] - float_bits(C.seed_c[q]);
     for (int q = 0; q < C.T; q++) o[kTapRecZ + q] = t[kTapRecZ + q] - float_bits(C.seed_c[2 * VP + q]);
-    // E = W - zoff M (mod 2^(32 NW)), sign-extended to five words
+    // E = W - zoff M (mod 2^(32 NW)): the kernel's accumulator holds only the
+    // low 32 NW bits of E (R = E - zhat M is all it needs, |R| < 2^113)
     unsigned __int128 W = 0, Rv = 0;
     for (int i = 0; i < NW; i++) {
       W |= (unsigned __int128)t[kTapRecW + i] << (32 * i);
       Rv |= (unsigned __int128)t[kTapRecR + i] << (32 * i);
     }
     unsigned __int128 E = (W - (unsigned __int128)C.zoff * M) & mask;
-    const bool eneg = (E >> (wbits - 1)) & 1, rneg = (Rv >> (wbits - 1)) & 1;
-    for (int i = 0; i < 5; i++) o[kTapRecW + i] = i < NW ? (uint32_t)(E >> (32 * i)) : (eneg ? ~0u : 0u);
+    const bool rneg = (Rv >> (wbits - 1)) & 1;
+    for (int i = 0; i < 5; i++) o[kTapRecW + i] = i < NW ? (uint32_t)(E >> (32 * i)) : 0u;
     for (int i = 0; i < 4; i++) o[kTapRecR + i] = i < NW ? (uint32_t)(Rv >> (32 * i)) : (rneg ? ~0u : 0u);
     o[kTapRecZhat] = t[kTapRecZhat] - C.zoff;
     o[kTapRecExp] = t[kTapRecExp];
@@ -841,22 +845,35 @@ extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* 
 // only the table (with the callers' pointers) is re-uploaded per call.
 static const int kPassStage[6] = {1, 2, 1, 2, 1, 2};
 
-extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
-                                                  const obfft_options_t* opt) {
+// opts: one options struct for every member (per_member == 0) or an array of
+// `count` (per_member == 1).
+static obfft_status_t batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
+                                        const obfft_options_t* opts, int per_member) {
   if (!out || count <= 0 || count > 65535 || !shapes) return OBFFT_INVALID_VALUE;
   *out = nullptr;
   obfft_options_t def;
   obfft_options_default(&def);
-  if (!opt) opt = &def;
-  if (opt->precision != OBFFT_PREC_FP64 || opt->reduction != OBFFT_RED_RECIPROCAL) return OBFFT_INVALID_VALUE;
+  if (!opts) {
+    opts = &def;
+    per_member = 0;
+  }
+  for (int i = 0; i < (per_member ? count : 1); i++)
+    if (opts[i].precision != OBFFT_PREC_FP64 || opts[i].reduction != OBFFT_RED_RECIPROCAL ||
+        opts[i].substrate != opts[0].substrate || opts[i].n_moduli_override || opts[i].moduli_override)
+      return OBFFT_INVALID_VALUE;
   obfft_plan_t bp = new (std::nothrow) obfft_plan_s();
   if (!bp) return OBFFT_ALLOC_FAILED;
   bp->batch_count = count;
-  // members share planes when their shapes coincide: plan each distinct shape once
-  std::map<std::tuple<int64_t, int64_t, int64_t>, obfft_plan_t> uniq;
+  // members share planes when their shapes and options coincide: plan each
+  // distinct (shape, factorisation, axis order, tile order) once
+  typedef std::tuple<int64_t, int64_t, int64_t, std::vector<int>> Key;
+  std::map<Key, obfft_plan_t> uniq;
   std::vector<obfft_plan_t> per(count);
   for (int i = 0; i < count; i++) {
-    auto key = std::make_tuple(shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
+    const obfft_options_t* opt = per_member ? &opts[i] : opts;
+    std::vector<int> ok = {opt->p[0], opt->p[1], opt->p[2], opt->q[0], opt->q[1], opt->q[2],
+                           opt->axis_order[0], opt->axis_order[1], opt->axis_order[2], opt->group_block};
+    Key key = std::make_tuple(shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2], ok);
     auto it = uniq.find(key);
     if (it == uniq.end()) {
       obfft_plan_t m = nullptr;
@@ -870,6 +887,11 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     }
     per[i] = it->second;
   }
+  for (int i = 1; i < count; i++)
+    if (per[i]->substrate != per[0]->substrate) {
+      obfft_plan_destroy(bp);
+      return OBFFT_INVALID_VALUE;
+    }
   bp->substrate = per[0]->substrate;
   bp->precision = OBFFT_PREC_FP64;
   for (int k = 0; k < 3; k++) bp->order[k] = per[0]->order[k];
@@ -967,8 +989,14 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     bp->persist_nseg = nseg;
     bp->persist_items = seg_start[nseg];
     bp->persist_lds = persist_lds_bytes(mask);
-    bp->persist_grid_size = persist_grid(bp->persist_lds);
-    if (bp->persist_grid_size <= 0 || seg_start[nseg] >= ((int64_t)1 << 32) - bp->persist_grid_size) {
+    bp->persist_mask = mask;
+    bp->persist_grid_size = persist_grid(mask, bp->persist_lds);
+    // claim size: about four chunks per workgroup over the batch, at most 64
+    // items (one publication, i.e. one L2 write-back, per chunk and segment)
+    bp->persist_claim = (int)std::max<int64_t>(
+        1, std::min<int64_t>(64, seg_start[nseg] / (4 * (int64_t)std::max(bp->persist_grid_size, 1))));
+    if (bp->persist_grid_size <= 0 ||
+        seg_start[nseg] >= ((int64_t)1 << 32) - (int64_t)bp->persist_grid_size * kMaxClaim) {
       obfft_plan_destroy(bp);
       return OBFFT_HIP_ERROR;
     }
@@ -988,6 +1016,7 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
     Q.seg_cls = bp->d_seg_cls;
     Q.nseg = nseg;
     Q.spin_limit = bp->persist_spin;
+    Q.claim = bp->persist_claim;
     Q.total = seg_start[nseg];
     Q.ctl = bp->d_ctl;
     Q.flags = bp->d_flags;
@@ -1000,16 +1029,26 @@ extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, 
       return OBFFT_HIP_ERROR;
     }
     bp->persist_ok = 1;
-    bp->batch_mode = OBFFT_BATCH_PERSISTENT;
   }
   *out = bp;
   return OBFFT_SUCCESS;
 }
 
+extern "C" obfft_status_t obfft_batch_plan_create(obfft_plan_t* out, int count, const int64_t* shapes,
+                                                  const obfft_options_t* opt) {
+  return batch_plan_create(out, count, shapes, opt, 0);
+}
+
+extern "C" obfft_status_t obfft_batch_plan_create_each(obfft_plan_t* out, int count, const int64_t* shapes,
+                                                       const obfft_options_t* opts) {
+  if (!opts) return OBFFT_INVALID_VALUE;
+  return batch_plan_create(out, count, shapes, opts, 1);
+}
+
 static obfft_status_t batch_launch_passes(obfft_plan_t bp, hipStream_t st) {
   int count = bp->batch_count;
   if (bp->batch_mode == OBFFT_BATCH_PERSISTENT)
-    return launch_persist(bp->d_persist, bp->d_ctl, 2 + bp->persist_nseg, bp->persist_grid_size, bp->persist_lds,
+    return launch_persist(bp->persist_mask, bp->d_persist, bp->d_ctl, 2 + bp->persist_nseg, bp->persist_grid_size, bp->persist_lds,
                           st) == hipSuccess
                ? OBFFT_SUCCESS
                : OBFFT_HIP_ERROR;
@@ -1107,6 +1146,21 @@ extern "C" obfft_status_t obfft_batch_set_poll_limit(obfft_plan_t plan, int poll
   if (hipMemcpy((char*)plan->d_persist + off, &polls, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return fail(plan, OBFFT_HIP_ERROR);
   return OBFFT_SUCCESS;
+}
+
+extern "C" obfft_status_t obfft_batch_set_claim(obfft_plan_t plan, int items) {
+  if (!plan || !plan->batch_count || items < 1 || items > kMaxClaim) return OBFFT_INVALID_VALUE;
+  if (!plan->persist_ok) return fail(plan, OBFFT_INVALID_VALUE);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(plan, OBFFT_HIP_ERROR);
+  plan->persist_claim = items;
+  const size_t off = offsetof(PersistParams, claim);
+  if (hipMemcpy((char*)plan->d_persist + off, &items, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(plan, OBFFT_HIP_ERROR);
+  return OBFFT_SUCCESS;
+}
+
+extern "C" int obfft_batch_get_claim(obfft_plan_t plan) {
+  return plan && plan->batch_count && plan->persist_ok ? plan->persist_claim : 0;
 }
 
 // Workspace of the batch (sum of the members', 256-byte aligned).

@@ -248,12 +248,15 @@ struct RegDft {
   }
 };
 
-template <int R1, int R2, bool STRIDED, int DIR>
-__global__ __launch_bounds__(kNatThreads) __attribute__((amdgpu_waves_per_eu(2))) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
+// NT threads per workgroup: 256, or 512 on a strided axis with R2 = 32, so
+// that a workgroup holds 16 lines and every global access of a wave covers
+// 16 neighbouring lines (256-byte runs instead of 128).
+template <int R1, int R2, bool STRIDED, int DIR, int NT = kNatThreads>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
                                                                    int64_t nlines, const double2* tw,
                                                                    double post_scale) {
   constexpr int N = R1 * R2;
-  constexpr int LPW = kNatThreads / R2;           // lines per workgroup
+  constexpr int LPW = NT / R2;                    // lines per workgroup
   constexpr int LS = ((R1 * (R2 + 1)) | 1);      // padded line stride in LDS (doubles, odd)
   __shared__ double plane[LPW * LS];
   const int tid = threadIdx.x;
@@ -333,15 +336,18 @@ template <int R1, int R2>
 static hipError_t launch_4step(const double2* in, double2* out, const NatAxis& A, int inverse, double ps,
                                hipStream_t st) {
   constexpr int LPW = kNatThreads / R2;
+  constexpr int NTS = R2 == 32 ? 2 * kNatThreads : kNatThreads;  // strided axes
+  constexpr int LPWS = NTS / R2;
   int64_t nlines = A.outer * A.inner;
   int64_t grid = (nlines + LPW - 1) / LPW;
   bool strided = A.inner > 1;
   if (strided) {
+    grid = (nlines + LPWS - 1) / LPWS;
     if (inverse)
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, -1>), dim3((unsigned)grid), dim3(kNatThreads), 0, st,
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, -1, NTS>), dim3((unsigned)grid), dim3(NTS), 0, st,
                          in, out, A.inner, nlines, A.tw, ps);
     else
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, 1>), dim3((unsigned)grid), dim3(kNatThreads), 0, st,
+      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, 1, NTS>), dim3((unsigned)grid), dim3(NTS), 0, st,
                          in, out, A.inner, nlines, A.tw, ps);
   } else {
     if (inverse)

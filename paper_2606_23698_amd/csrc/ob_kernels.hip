@@ -97,108 +97,145 @@ static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, 
 // the launch cannot deadlock, whatever the grid.  A wait that exceeds the
 // plan's poll limit raises the give-up flag, and every workgroup then leaves
 // at its next poll or claim, so the kernel always ends.
-__device__ __forceinline__ void persist_run_tile(int cls, const StageParams& P, int64_t c, int64_t g) {
-  switch (cls) {
-    case kPersistK4Packed: stage_tile<SUB_FP16, 0, 16, true, false, 4>(P, c, g); break;
-    case kPersistK8Packed: stage_tile<SUB_FP16, 0, 16, true, false, 2>(P, c, g); break;
-    case kPersistK12Full: stage_tile<SUB_FP16, 0, 12, true>(P, c, g); break;
-    case kPersistK12: stage_tile<SUB_FP16, 0, 12, false>(P, c, g); break;
-    case kPersistK16Full: stage_tile<SUB_FP16, 0, 16, true>(P, c, g); break;
-    case kPersistK16: stage_tile<SUB_FP16, 0, 16, false>(P, c, g); break;
-    case kPersistK32Full: stage_tile<SUB_FP16, 0, 32, true>(P, c, g); break;
-    default: stage_tile<SUB_FP16, 0, 32, false>(P, c, g); break;
-  }
+// MASK: the tile variants (bit v = kPersist* v) the kernel carries.  One
+// body holding all eight spills registers, so the plan launches the
+// instantiation with the fewest variants that covers its members.
+template <unsigned MASK, class PT>
+__device__ __forceinline__ void persist_run_tile(int cls, const PT& P, int64_t c, int64_t g) {
+  if ((MASK >> kPersistK4Packed & 1) && cls == kPersistK4Packed) stage_tile<SUB_FP16, 0, 16, true, false, 4>(P, c, g);
+  else if ((MASK >> kPersistK8Packed & 1) && cls == kPersistK8Packed) stage_tile<SUB_FP16, 0, 16, true, false, 2>(P, c, g);
+  else if ((MASK >> kPersistK12Full & 1) && cls == kPersistK12Full) stage_tile<SUB_FP16, 0, 12, true>(P, c, g);
+  else if ((MASK >> kPersistK12 & 1) && cls == kPersistK12) stage_tile<SUB_FP16, 0, 12, false>(P, c, g);
+  else if ((MASK >> kPersistK16Full & 1) && cls == kPersistK16Full) stage_tile<SUB_FP16, 0, 16, true>(P, c, g);
+  else if ((MASK >> kPersistK16 & 1) && cls == kPersistK16) stage_tile<SUB_FP16, 0, 16, false>(P, c, g);
+  else if ((MASK >> kPersistK32Full & 1) && cls == kPersistK32Full) stage_tile<SUB_FP16, 0, 32, true>(P, c, g);
+  else if (MASK >> kPersistK32 & 1) stage_tile<SUB_FP16, 0, 32, false>(P, c, g);
 }
 
 // The parameters live in device memory and are re-read per item (scalar
 // loads) rather than held in registers across the tile body.
 //
-// Ordering: every wave fences its own stores at agent scope (release) before
-// the end-of-tile barrier, because the barrier itself does not wait for
-// outstanding vector stores; thread 0 then publishes the tile with a release
-// add.  A waiter polls with relaxed loads and, once the dependency is
-// complete, every wave takes one acquire fence before the tile reads its
-// input.  A workgroup remembers the last dependency it has seen complete (it
-// stays complete for the rest of the launch), so consecutive tiles of one
-// segment poll and fence once.
+// Claims: a workgroup takes `claim` consecutive items at a time.  Making a
+// tile's stores visible to the other XCDs takes an agent-scope release,
+// which on this part writes back the XCD's L2; one such release per tile
+// costs more than the tile itself, so a workgroup publishes its finished
+// tiles of a segment together: when the chunk ends, and whenever the next
+// item belongs to another segment (before waiting for that segment's
+// dependency, so that no tile is held unpublished while its workgroup
+// waits).  Every wave fences its own stores at agent scope (release) before
+// the barrier, because the barrier does not wait for outstanding vector
+// stores; thread 0 then adds the count with a release add.  A waiter polls
+// with relaxed loads and, once the dependency is complete, every wave takes
+// one acquire fence before the tile reads its input.  A workgroup remembers
+// the last dependency it has seen complete (it stays complete for the rest
+// of the launch).
+//
+// Deadlock freedom: chunks are claimed in increasing item order, a wait is
+// entered only with nothing unpublished, and every dependency lies in an
+// earlier pass (smaller items); the workgroup holding the smallest
+// unpublished item is therefore never waiting, and the launch drains
+// whatever the grid.
+__device__ __forceinline__ void persist_publish(const PersistParams* Qp, int seg, uint32_t n) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    OB_GLOBAL uint32_t* ctl = (OB_GLOBAL uint32_t*)((const OB_CONST PersistParams*)Qp)->ctl;
+    __hip_atomic_fetch_add(&ctl[2 + seg], n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <unsigned MASK>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_persist_kernel(
     const PersistParams* __restrict__ Qp) {
   __shared__ int64_t s_item;
-  __shared__ int s_go, s_seg, s_ready;
+  __shared__ int s_go, s_ready;
   if (threadIdx.x == 0) s_ready = -1;
-  for (;;) {
+  bool stop = false;
+  while (!stop) {
     const PersistParams* Qg = Qp;
     asm volatile("" : "+s"(Qg));  // the parameter block is re-read after every tile
     const OB_CONST PersistParams* Q = (const OB_CONST PersistParams*)Qg;  // scalar loads
     OB_GLOBAL uint32_t* ctl = (OB_GLOBAL uint32_t*)Q->ctl;
     const int64_t total = Q->total;
+    const int claim = Q->claim;
     if (threadIdx.x == 0) {
-      const bool stop = __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-      s_item = stop ? total : (int64_t)__hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
+      const bool gave_up = __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      s_item = gave_up ? total
+                       : (int64_t)__hip_atomic_fetch_add(&ctl[0], (uint32_t)claim, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    const int64_t it = s_item;
-    if (it >= total) break;
-    // the segment of item `it`: the last d with seg_start[d] <= it
+    const int64_t base = s_item;
+    if (base >= total) break;
+    const int64_t end = min(base + (int64_t)claim, total);
+    // the segment of item `base`: the last d with seg_start[d] <= base
     const OB_CONST int64_t* seg_start = (const OB_CONST int64_t*)Q->seg_start;
     int lo = 0, hi = Q->nseg - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (seg_start[mid] <= it) lo = mid;
+      if (seg_start[mid] <= base) lo = mid;
       else hi = mid - 1;
     }
-    const int d = __builtin_amdgcn_readfirstlane(lo);
-    if (threadIdx.x == 0) {
-      int go = 1;  // 0: leave, 1: run, 2: run after an acquire fence
-      const int dep = ((const OB_CONST int*)Q->seg_dep)[d];
-      if (dep >= 0 && dep != s_ready) {
-        const uint32_t need = (uint32_t)(seg_start[dep + 1] - seg_start[dep]);
-        const int limit = Q->spin_limit;
-        for (int k = 0;; k++) {
-          if (__hip_atomic_load(&ctl[2 + dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
-            go = 2;
-            s_ready = dep;
-            break;
+    int d = __builtin_amdgcn_readfirstlane(lo);
+    int cur = -1;          // segment whose finished tiles await publication
+    uint32_t pending = 0;  // how many
+    for (int64_t it = base; it < end; it++) {
+      while (seg_start[d + 1] <= it) d++;  // items ascend: the segment only moves forward
+      d = __builtin_amdgcn_readfirstlane(d);
+      if (d != cur) {
+        if (pending) persist_publish(Qp, cur, pending);
+        pending = 0;
+        cur = d;
+        if (threadIdx.x == 0) {
+          int go = 1;  // 0: leave, 1: run, 2: run after an acquire fence
+          const int dep = ((const OB_CONST int*)Q->seg_dep)[d];
+          if (dep >= 0 && dep != s_ready) {
+            const uint32_t need = (uint32_t)(seg_start[dep + 1] - seg_start[dep]);
+            const int limit = Q->spin_limit;
+            for (int k = 0;; k++) {
+              if (__hip_atomic_load(&ctl[2 + dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+                go = 2;
+                s_ready = dep;
+                break;
+              }
+              if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                go = 0;
+                break;
+              }
+              if (k >= limit) {
+                __hip_atomic_store(&ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or((OB_GLOBAL uint32_t*)Q->flags, 2u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                go = 0;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(4);
+            }
           }
-          if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            go = 0;
-            break;
-          }
-          if (k >= limit) {
-            __hip_atomic_store(&ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_or((OB_GLOBAL uint32_t*)Q->flags, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            go = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(4);
+          s_go = go;
         }
+        __syncthreads();
+        const int go = s_go;
+        if (!go) {
+          stop = true;
+          break;
+        }
+        if (go == 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      s_go = go;
-      s_seg = d;
+      const int64_t local = it - seg_start[d];
+      const int cls = ((const OB_CONST int*)Q->seg_cls)[d];
+      // the descriptor stays in memory: its fields are scalar loads where used
+      const OB_CONST StageParams& P = ((const OB_CONST StageParams*)Q->descs)[d];
+      int64_t c, g;
+      decode_tile(P, local, c, g);
+      persist_run_tile<MASK>(cls, P, c, g);
+      pending++;
+      // the next tile rewrites the LDS column tables and digit buffers that
+      // slower waves of this one may still read (its epilogue reads the
+      // output columns and exponents)
+      __syncthreads();
     }
-    __syncthreads();
-    const int go = s_go;
-    if (!go) break;
-    if (go == 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int64_t local = it - seg_start[d];
-    const int cls = ((const OB_CONST int*)Q->seg_cls)[d];
-#if defined(__HIP_DEVICE_COMPILE__)
-    const StageParams P = ((const OB_CONST StageParams*)Q->descs)[d];  // scalar loads
-#else
-    const StageParams P = Q->descs[d];  // (host parse only)
-#endif
-    int64_t c, g;
-    decode_tile(P, local, c, g);
-    persist_run_tile(cls, P, c, g);
-    // this wave's stores are complete and visible at agent scope before the
-    // barrier; then one release add publishes the tile
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      OB_GLOBAL uint32_t* ctl2 = (OB_GLOBAL uint32_t*)((const OB_CONST PersistParams*)Qp)->ctl;
-      __hip_atomic_fetch_add(&ctl2[2 + s_seg], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (pending) persist_publish(Qp, cur, pending);
   }
 }
 
@@ -230,18 +267,28 @@ int persist_variant(int K) {
   return K == 32 ? kPersistK32Full : kPersistK32;
 }
 
-// Workgroups of the persistent launch: what the device holds at once.
-int persist_grid(int lds) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)ob_persist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024) != hipSuccess)
-      return -1;
-    attr_set = true;
+// Instantiations of the persistent kernel: the full-length and packed
+// variants only (every member's contraction lengths are <= 8, 12, 16 or 32:
+// all power-of-two extents and the 12-point factors), and all eight.
+static const void* persist_kernel(unsigned mask) {
+  return (mask & ~kPersistMaskFull) == 0 ? (const void*)ob_persist_kernel<kPersistMaskFull>
+                                         : (const void*)ob_persist_kernel<kPersistMaskAll>;
+}
+
+// Workgroups of the persistent launch: what the device holds at once.  The
+// kernel has a few bytes of static LDS of its own, so the dynamic maximum is
+// raised only to what the tile variants need (at most 20 KB), never to the
+// whole 160 KB of the CU.
+int persist_grid(unsigned mask, int lds) {
+  static int attr_lds[2] = {0, 0};
+  const void* k = persist_kernel(mask);
+  const int ki = k == (const void*)ob_persist_kernel<kPersistMaskFull> ? 0 : 1;
+  if (lds > attr_lds[ki]) {
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+    attr_lds[ki] = lds;
   }
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ob_persist_kernel, kThreads, lds) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess ||
       hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return -1;
@@ -250,12 +297,15 @@ int persist_grid(int lds) {
 
 // The control block is cleared by a kernel (not a memset), so that the pair
 // can be captured in a graph and replayed.
-hipError_t launch_persist(const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
+hipError_t launch_persist(unsigned mask, const PersistParams* Q, uint32_t* ctl, int64_t ctl_words, int grid, int lds,
                           hipStream_t st) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((ctl_words + 255) / 256)), dim3(256), 0, st, ctl, ctl_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ob_persist_kernel, dim3((unsigned)grid), dim3(kThreads), lds, st, Q);
+  if ((mask & ~kPersistMaskFull) == 0)
+    hipLaunchKernelGGL(ob_persist_kernel<kPersistMaskFull>, dim3((unsigned)grid), dim3(kThreads), lds, st, Q);
+  else
+    hipLaunchKernelGGL(ob_persist_kernel<kPersistMaskAll>, dim3((unsigned)grid), dim3(kThreads), lds, st, Q);
   return hipGetLastError();
 }
 

@@ -209,7 +209,8 @@ __device__ __forceinline__ uint32_t udiv31(uint32_t n, uint32_t magic, uint32_t 
 // column tiles c = 8 j + x, and for one block of gblock groups at a time
 // runs those groups of a column tile back to back, so that the partial lines
 // merge in that L2 while only gblock groups' matrix planes are live in it.
-__device__ __forceinline__ void decode_tile(const StageParams& P, int64_t tile, int64_t& c, int64_t& g) {
+template <class PT>  // StageParams in any address space
+__device__ __forceinline__ void decode_tile(const PT& P, int64_t tile, int64_t& c, int64_t& g) {
   if (P.stage == 1) {
     c = tile;
     g = 0;
@@ -264,8 +265,11 @@ __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int6
 // TAP: the debug variant, which also writes the canonical residues of every
 // output (P.dbg_res) and the epilogue record of every output of one line
 // (P.dbg_tap, P.dbg_line); the production kernels are built without it.
-template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false, int NP = 1, bool TAP = false>
-__device__ __forceinline__ void stage_tile(const StageParams& P, int64_t ctile, int64_t g) {
+// PT: StageParams in any address space (a kernel argument, or a descriptor
+// in the constant space read field by field where it is used).
+template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false, int NP = 1, bool TAP = false,
+          class PT = StageParams>
+__device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;

@@ -149,6 +149,8 @@ struct PersistParams {
   const int* seg_cls;        // [nseg] tile variant (kPersist* below)
   int nseg;
   int spin_limit;            // polls of a dependency before the kernel gives up
+  int claim;                 // items a workgroup claims at once (>= 1)
+  int pad_;
   int64_t total;             // items
   uint32_t* ctl;             // [0] item counter, [1] give-up flag, [2 + seg] tiles completed
   uint32_t* flags;           // the plan's status word: bit 1 = a dependency wait gave up
@@ -163,6 +165,9 @@ enum {
   kPersistK32Full = 6, kPersistK32 = 7,
   kPersistVariants = 8
 };
+constexpr unsigned kPersistMaskFull = (1u << kPersistK4Packed) | (1u << kPersistK8Packed) | (1u << kPersistK12Full) |
+                                      (1u << kPersistK16Full) | (1u << kPersistK32Full);
+constexpr unsigned kPersistMaskAll = (1u << kPersistVariants) - 1;
 
 // Plan-time per-(N, p, q) operand set for one stage direction.
 struct OperandPlanes {

@@ -1,6 +1,6 @@
-"""Batched uneven transforms: one persistent launch over every Bailey pass of
-every member (or one launch per pass and contraction class), replayed from a
-hipGraph.
+"""Batched uneven transforms: one launch per Bailey pass and contraction
+class (the default) or one persistent launch over every pass of every
+member, replayed from a hipGraph.
 
 Every member's output must be bit-identical to the single-transform path
 (the same plan, factorisation and axis order), in both modes, on several
@@ -72,6 +72,11 @@ def test_batch_64_uneven_workload(gpu):
     torch.cuda.synchronize()
     for i, (s, x, o) in enumerate(zip(shapes, xs, outs)):
         assert torch.equal(o, api.get_plan(s).forward(x)), (i, s)
+    bp.set_mode("persistent")
+    outp = bp.forward(xs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(outp, outs)):
+        assert torch.equal(a, b), (i, shapes[i])
     smallest = sorted(range(len(shapes)), key=lambda i: int(np.prod(shapes[i])))[:3]
     for i in smallest:
         plan = api.get_plan(shapes[i])
@@ -89,6 +94,7 @@ def test_persistent_batch_gives_up_when_told(gpu):
     xs = [torch.from_numpy(inputs.uniform(s, 40 + i)).to(gpu) for i, s in enumerate(shapes)]
     ref = [api.get_plan(s).forward(x) for s, x in zip(shapes, xs)]
     bp = api.BatchPlan(shapes)
+    bp.set_mode("persistent")
     bp.set_poll_limit(0)
     bp.forward(xs)
     torch.cuda.synchronize()
@@ -100,3 +106,50 @@ def test_persistent_batch_gives_up_when_told(gpu):
     torch.cuda.synchronize()
     for o, r in zip(outs, ref):
         assert torch.equal(o, r)
+
+
+def test_batch_with_tuned_member_options(gpu, tmp_path, monkeypatch):
+    """Per-member options (the autotuner's factorisation and tile order per
+    shape): each member equals fft3d_z2z_forward on a single plan made with
+    its own options, bit for bit, in both modes; and one member's options
+    change only that member's bits."""
+    from paper_2606_23698_amd import api, autotune
+    monkeypatch.setenv("OBFFT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    shapes = [(16, 96, 64), (32, 48, 24), (16, 96, 64), (12, 40, 8)]
+    mo = autotune.tune_batch(shapes, reps=1)
+    assert mo[0] == mo[2]
+    # a forced, unbalanced split of the second member (K = 3 and 16 on its n3 axis)
+    mo[1] = {"pq": [(4, 8), (3, 16), (3, 8)], "group_block": 0}
+    xs = [torch.from_numpy(inputs.uniform(s, 60 + i)).to(gpu) for i, s in enumerate(shapes)]
+    refs = [api.Plan(s, substrate="fp16", pq=m["pq"], group_block=m["group_block"]).forward(x)
+            for s, m, x in zip(shapes, mo, xs)]
+    for mode in ("persistent", "passes"):
+        bp = api.BatchPlan(shapes, substrate="fp16", member_options=mo)
+        bp.set_mode(mode)
+        outs = bp.forward(xs)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, r), (mode, i, shapes[i], mo[i])
+    default = api.get_plan(shapes[1]).forward(xs[1])
+    torch.cuda.synchronize()
+    assert not torch.equal(default, refs[1])   # another split rounds elsewhere
+
+
+def test_persistent_claim_sizes(gpu):
+    """Every claim size of the persistent launch (tiles a workgroup takes and
+    publishes together) gives the single transforms' bits, on members whose
+    passes span one to hundreds of tiles."""
+    from paper_2606_23698_amd import api
+    shapes = [(64, 96, 128), (16, 16, 16), (96, 64, 32), (8, 256, 8), (32, 32, 32)]
+    xs = [torch.from_numpy(inputs.uniform(s, 70 + i)).to(gpu) for i, s in enumerate(shapes)]
+    ref = [api.get_plan(s).forward(x) for s, x in zip(shapes, xs)]
+    bp = api.BatchPlan(shapes)
+    assert 1 <= bp.claim() <= 64
+    for c in (1, 2, 3, 7, 64, 256):
+        bp.set_claim(c)
+        assert bp.claim() == c
+        for rep in range(2):
+            outs = bp.forward(xs)
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, ref)):
+                assert torch.equal(o, r), (c, rep, i, shapes[i])

@@ -4,7 +4,9 @@ the non-finite input flag, the axis-order option and in-place execution.
 * Debug tap (Alg. 2 checkpoints of one line): the residues that entered
   Phase A are congruent to the oracle's exact stage integers modulo every m_k
   and centred; P_s, Z_t, E, zhat and R equal the big-integer CRT reference
-  (Sec. 4.2, Eqs. fcrt and slicing; Sec. 5.1) evaluated on those residues;
+  (Sec. 4.2, Eqs. fcrt and slicing; Sec. 5.1) evaluated on those residues
+  (E modulo 2^128, or 2^96 for the FP32 target: the low words the kernel's
+  accumulator holds);
   R equals the oracle's exact integer and the output bits the oracle's.
 * A non-finite input raises OBFFT_NONFINITE_INPUT through obfft_last_error
   and the kernels still finish; a finite call afterwards reports success.
@@ -61,7 +63,9 @@ def _check_tap(dump, ref, moduli, precision):
             assert [int(np.int32(rec[s])) for s in range(S)] == P, (t, part)
             assert [int(np.int32(rec[16 + q])) for q in range(T)] == Z, (t, part)
             E = sum(p << (8 * s) for s, p in enumerate(P))
-            assert words_to_int([int(w) for w in rec[24:29]], signed=True) == E, (t, part)
+            nw = 4 if precision == 0 else 3   # the accumulator holds E mod 2^(32 nw)
+            assert words_to_int([int(w) for w in rec[24:24 + nw]], signed=False) == E % (1 << (32 * nw)), (t, part)
+            assert all(int(w) == 0 for w in rec[24 + nw:29]), (t, part)
             zh = crt_ref.zhat_from(Z)
             assert int(np.int32(rec[29])) == zh, (t, part)
             R = words_to_int([int(w) for w in rec[30:30 + nR]], signed=True)
@@ -138,11 +142,13 @@ def test_nonfinite_input_sets_the_flag(gpu):
     assert torch.equal(y, ok)
 
 
-def test_nonfinite_input_flag_in_a_batch(gpu):
+@pytest.mark.parametrize("mode", ["passes", "persistent"])
+def test_nonfinite_input_flag_in_a_batch(gpu, mode):
     api = _api()
     shapes = [(8, 16, 32), (16, 16, 16)]
     xs = [torch.from_numpy(inputs.uniform(s, 30 + i)).to(gpu) for i, s in enumerate(shapes)]
     bp = api.BatchPlan(shapes)
+    bp.set_mode(mode)
     bp.forward(xs)
     torch.cuda.synchronize()
     assert bp.last_error() == 0
