@@ -80,8 +80,9 @@ static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, 
       return F && full ? launch_batch_t<SUB, 16, F>(descs, first, tmember, total, st)
                        : launch_batch_t<SUB, 16, false>(descs, first, tmember, total, st);
     default:
-      return F && full ? launch_batch_t<SUB, 32, F>(descs, first, tmember, total, st)
-                       : launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
+      // FP8: `full` also says that the modulus set follows the full-length tile's digit rule
+      return (F || SUB == SUB_FP8) && full ? launch_batch_t<SUB, 32, true>(descs, first, tmember, total, st)
+                                           : launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
   }
 }
 
@@ -314,7 +315,7 @@ hipError_t launch_batch(int sub, int kmax, bool full, const StageParams* descs, 
                         const uint16_t* tmember, int64_t total, hipStream_t st) {
   if (sub == SUB_FP16) return launch_batch_s<SUB_FP16>(kmax, full, descs, first, tmember, total, st);
   if (sub == SUB_INT8) return launch_batch_s<SUB_INT8>(kmax, false, descs, first, tmember, total, st);
-  return launch_batch_s<SUB_FP8>(kmax, false, descs, first, tmember, total, st);
+  return launch_batch_s<SUB_FP8>(kmax, full && kmax == 32, descs, first, tmember, total, st);
 }
 
 // Columns per workgroup of the stage kernel for contraction length K.

@@ -153,3 +153,17 @@ def test_persistent_claim_sizes(gpu):
             torch.cuda.synchronize()
             for i, (o, r) in enumerate(zip(outs, ref)):
                 assert torch.equal(o, r), (c, rep, i, shapes[i])
+
+
+def test_fp8_batch_with_full_length_members(gpu):
+    """FP8 batches (one launch per pass and class): a class of K = 32 stages
+    takes the full-length FP8 tile; outputs equal the single FP8 plans."""
+    from paper_2606_23698_amd import api
+    shapes = [(2, 4, 1024), (4, 4, 32), (3, 1024, 2)]
+    xs = [torch.from_numpy(inputs.uniform(s, 80 + i)).to(gpu) for i, s in enumerate(shapes)]
+    ref = [api.Plan(s, substrate="fp8").forward(x) for s, x in zip(shapes, xs)]
+    bp = api.BatchPlan(shapes, substrate="fp8")
+    outs = bp.forward(xs)
+    torch.cuda.synchronize()
+    for o, r, s in zip(outs, ref, shapes):
+        assert torch.equal(o, r), s

@@ -87,6 +87,7 @@ def _check_tap(dump, ref, moduli, precision):
     ((32, 32, 32), "fp8", "fp64"),
     ((32, 32, 32), "int8", "fp64"),
     ((8, 12, 16), "fp16", "fp64"),
+    ((2, 2, 1024), "fp8", "fp64"),           # the full-length FP8 tile (K = 32)
     ((16, 8, 32), "fp16", "fp32"),
 ])
 def test_debug_tap_checkpoints_against_crt_reference(gpu, shape, substrate, precision):

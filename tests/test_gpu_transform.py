@@ -186,3 +186,49 @@ def test_native_fp64_fft_accuracy(gpu):
         assert rel_l2(y, hi, lo) <= 1e-14, shape
         back = _run(plan, y, gpu, "native_inverse")
         assert rel_l2(back, x) <= 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fp8_full_length_tile_bit_exact(gpu, precision):
+    """Stages of contraction length 32 on the FP8 substrate (the full-length
+    tile with three digits per residue before the split and two after it)
+    against the oracle, with a ragged third axis for the general tile."""
+    api = _api()
+    shape = (3, 32, 1024)
+    pq = ((1, 3), (1, 32), (32, 32))
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    x = inputs.uniform(shape, 13).astype(dt)
+    plan = api.Plan(shape, precision=precision, substrate="fp8", pq=pq)
+    y = _run(plan, x, gpu)
+    ref = ox.fft3_exact(x, _pq(plan), precision=0 if precision == "fp64" else 1)
+    assert np.count_nonzero(y != ref) == 0
+
+
+def test_fp8_general_tile_at_k32(gpu):
+    """A modulus set outside the full-length tile's digit rule (1089, three
+    digits, after the split) runs the general FP8 tile at K = 32: the same
+    bits as the default plan."""
+    api = _api()
+    shape = (2, 8, 1024)
+    x = inputs.uniform(shape, 14)
+    mods = [2039, 2029, 2027, 1024, 1089, 961, 841, 625, 529, 511, 491, 487]
+    y0 = _run(api.Plan(shape), x, gpu)
+    y1 = _run(api.Plan(shape, substrate="fp8", moduli=mods), x, gpu)
+    assert np.array_equal(y0, y1)
+
+
+@pytest.mark.parametrize("shape", [(64, 32, 1024), (3, 1024, 40), (1024, 6, 11), (5, 7, 1024)])
+def test_tile_loop_bit_identical(gpu, shape):
+    """The prefetching tile loop (full-length FP16 K = 32 stages: resident
+    workgroups walk the tiles and fetch the next tile's input into LDS during
+    the epilogue) gives the one-workgroup-per-tile launch's bits: several
+    tiles per workgroup, group-major and group-minor stage-2 orders, ragged
+    last tiles; and the oracle's on the smallest."""
+    api = _api()
+    x = inputs.uniform(shape, 15)
+    y0 = _run(api.Plan(shape), x, gpu)
+    y1 = _run(api.Plan(shape, tile_loop=1), x, gpu)
+    assert np.array_equal(y0, y1)
+    if np.prod(shape) <= 40000:
+        plan = api.Plan(shape, tile_loop=1)
+        assert np.count_nonzero(y1 != ox.fft3_exact(x, _pq(plan))) == 0
