@@ -32,8 +32,9 @@ SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
 # profiles/ob_stage_kernel_fp16_1024cubed_counters.md; valid only for the
 # kernel sources they were taken with (fingerprint below), else null.
 TRAFFIC_MEASURED = {"bytes": 34.63e9, "sources_sha256_16": "f29841231d8c46e0"}
-KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_device.h",
-                  "paper_2606_23698_amd/csrc/ob_recon.h", "paper_2606_23698_amd/csrc/obfft_internal.h"]
+KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_stage.h",
+                  "paper_2606_23698_amd/csrc/ob_device.h", "paper_2606_23698_amd/csrc/ob_recon.h",
+                  "paper_2606_23698_amd/csrc/obfft_internal.h"]
 
 
 def measured_traffic(N, substrate):

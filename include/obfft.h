@@ -117,11 +117,7 @@ typedef struct {
                                {0, 1, 2}; all zero = library default {2, 1, 0} (n3, then n2,
                                then n1).  Changes output bits (every axis pass rounds once
                                per stage), so the plan records it. */
-  int tile_loop;            /* 1: stages with a full-length FP16 K = 32 tile (FP64 target) run as a
-                               tile loop over resident workgroups that fetches the next tile's
-                               input into LDS during the current tile's epilogue; 0 (default):
-                               one workgroup per tile.  Changes speed only, never results. */
-  int reserved[2];
+  int reserved[3];
 } obfft_options_t;
 
 typedef struct {

@@ -26,8 +26,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("substrate", ctypes.c_int), ("p", ctypes.c_int * 3),
                 ("q", ctypes.c_int * 3), ("n_moduli_override", ctypes.c_int),
                 ("moduli_override", ctypes.POINTER(ctypes.c_int32)), ("reduction", ctypes.c_int),
-                ("group_block", ctypes.c_int), ("axis_order", ctypes.c_int * 3), ("tile_loop", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("group_block", ctypes.c_int), ("axis_order", ctypes.c_int * 3), ("reserved", ctypes.c_int * 3)]
 
 
 class TapsLayout(ctypes.Structure):

@@ -50,14 +50,13 @@ def _check_dev(t, dtype, numel=None, name="tensor"):
 
 
 def options(precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal", group_block=0,
-            axis_order=None, tile_loop=0):
+            axis_order=None):
     opt = L.Options()
     L.lib().obfft_options_default(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
     opt.substrate = SUBSTRATES[substrate]
     opt.reduction = REDUCTIONS[reduction]
     opt.group_block = int(group_block)
-    opt.tile_loop = int(tile_loop)
     if axis_order is not None:
         for k, a in enumerate(axis_order):
             opt.axis_order[k] = int(a)
@@ -77,12 +76,12 @@ class Plan:
     """An Ozaki-Bailey 3-D FFT plan for one shape on the current device."""
 
     def __init__(self, shape, precision="fp64", substrate="auto", pq=None, moduli=None, reduction="reciprocal",
-                 group_block=0, axis_order=None, tile_loop=0):
+                 group_block=0, axis_order=None):
         self.shape = tuple(int(n) for n in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must have three extents")
         self.precision = precision
-        opt, keep = options(precision, substrate, pq, moduli, reduction, group_block, axis_order, tile_loop)
+        opt, keep = options(precision, substrate, pq, moduli, reduction, group_block, axis_order)
         h = ctypes.c_void_p()
         L.check(L.lib().obfft_plan_create(ctypes.byref(h), *self.shape, ctypes.byref(opt)),
                 "obfft_plan_create")

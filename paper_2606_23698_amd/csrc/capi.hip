@@ -56,7 +56,6 @@ struct obfft_plan_s {
   int reduction = OBFFT_RED_RECIPROCAL;
   int group_block = 0;  // 0: the library's choice
   int fp8_full = 0;     // the modulus set follows the full-length FP8 tile's digit rule
-  int tile_loop = 0;    // full-length FP16 K = 32 stages as the prefetching tile loop
   int order[3] = {2, 1, 0};  // axes in execution order (0 = n1)
   ModSet H;
   CrtConsts C;
@@ -202,8 +201,6 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   // the fold-and-add reduction is an ablation of the default FP64 path
   plan->reduction = opt->reduction;
   plan->group_block = opt->group_block;
-  if (opt->tile_loop != 0 && opt->tile_loop != 1) return OBFFT_INVALID_VALUE;
-  plan->tile_loop = opt->tile_loop;
   if (opt->axis_order[0] | opt->axis_order[1] | opt->axis_order[2])
     for (int k = 0; k < 3; k++) plan->order[k] = opt->axis_order[k];
   if (opt->reduction == OBFFT_RED_H0 && (sub != OBFFT_SUB_FP16 || plan->precision != OBFFT_PREC_FP64))
@@ -489,7 +486,6 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   P.crt = plan->d_crt;
   P.nf_flag = plan->d_flags;
   P.fp8_full = plan->fp8_full;
-  P.tile_loop = plan->tile_loop;
   if (stage == 1) {
     P.K = (int)q;
     P.G = (int)p;
@@ -514,10 +510,6 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
     const int gb = plan->group_block > 0 && q % plan->group_block == 0 ? plan->group_block : kGroupBlock;
     P.gblock = (q % gb) == 0 ? gb : (int)q;
     grid = (int64_t)P.tiles_per_g * q;
-    const int64_t T = P.tiles_per_g;
-    div_magic(T, &P.T_magic, &P.T_shift);
-    div_magic((T & 7) == 0 ? (T >> 3) * P.gblock : T * P.gblock, &P.blk_magic, &P.blk_shift);
-    div_magic(P.gblock, &P.gb_magic, &P.gb_shift);
   }
 }
 

@@ -27,8 +27,6 @@
 // runs on 64 outputs at a time (two 32x32x16 FP16 MFMAs fed by a cross-half
 // lane swap of the records, then one swap of the partials back), followed by
 // the integer epilogue and one coalesced 16-byte store per complex output.
-#include <algorithm>
-
 #include "ob_recon.h"
 
 namespace obfft {
@@ -267,28 +265,6 @@ __device__ __forceinline__ void decode_tile(const PT& P, int64_t tile, int64_t& 
   }
 }
 
-// decode_tile by multiply-high divisions (tile < 2^31): the tile loop keeps
-// no division state across its iterations.
-template <class PT>
-__device__ __forceinline__ void decode_tile32(const PT& P, uint32_t tile, uint32_t& c, uint32_t& g) {
-  if (P.stage == 1) {
-    c = tile;
-    g = 0;
-  } else if (!P.g_minor) {
-    g = udiv31(tile, P.T_magic, P.T_shift);
-    c = tile - g * (uint32_t)P.tiles_per_g;
-  } else {
-    const uint32_t T = (uint32_t)P.tiles_per_g, GB = (uint32_t)P.gblock;
-    const bool by8 = (T & 7) == 0;
-    const uint32_t x = by8 ? (tile & 7) : 0u, slot = by8 ? (tile >> 3) : tile;
-    const uint32_t blk = udiv31(slot, P.blk_magic, P.blk_shift);
-    const uint32_t rem = slot - blk * (by8 ? (T >> 3) * GB : T * GB);
-    const uint32_t rq = udiv31(rem, P.gb_magic, P.gb_shift);
-    g = blk * GB + (rem - rq * GB);
-    c = by8 ? rq * 8 + x : rq;
-  }
-}
-
 // The same order read off a 1-, 2- or 3-D grid without divisions (grid_mode):
 // the hardware's linear workgroup order is x fastest, then y, then z.
 __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int64_t& g) {
@@ -312,40 +288,6 @@ __device__ __forceinline__ void grid_tile(const StageParams& P, int64_t& c, int6
   }
 }
 
-// Input element offset of column c of a stage (stage 2: of group g), or -1
-// past the last column: c = (i, g, o), i fastest.
-template <class PT>
-__device__ __forceinline__ int64_t column_in(const PT& P, int64_t c, int64_t g) {
-  if (c >= P.ncols) return -1;
-  const uint32_t c32 = (uint32_t)c;  // ncols < 2^31 (checked by the plan)
-  const uint32_t rest = udiv31(c32, P.inner_magic, P.inner_shift);
-  const int64_t i = (int64_t)(c32 - rest * (uint32_t)P.inner);
-  int64_t o, gg;
-  if (P.stage == 1) {
-    const uint32_t q = udiv31(rest, P.G_magic, P.G_shift);
-    gg = rest - q * (uint32_t)P.G;
-    o = q;
-  } else {
-    gg = g;
-    o = rest;
-  }
-  return o * P.s_o + gg * P.s_in_g + i;
-}
-
-// Prefetching tile loop (PF): the input of a tile is staged in LDS by the
-// tile before it.  Thread t owns KQ 16-byte slots, slot u at
-// kPfOff + (u kThreads + t) 16: the wave's u-th global_load_lds_dwordx4 writes
-// 16 bytes per lane at consecutive addresses, so every thread reads back
-// exactly what its own lane loaded (no barrier; one wait on its own loads).
-template <int SUB, int TGT, int KMAX>
-__host__ __device__ constexpr int pf_offset() {
-  return align16(StageLds<SUB, TGT, KMAX>::bytes(KMAX));
-}
-template <int KMAX>
-__host__ __device__ constexpr int pf_bytes() {
-  return Shape<KMAX>::KQ * kThreads * 16;
-}
-
 // H0: the residue reduction after the GEMM takes the fold-and-add form for
 // the friendly moduli (FP16 substrate; the reciprocal form otherwise).
 // NP > 1: NP columns of a K <= 16 / NP stage per 16-row tile (fp16_pack): the
@@ -357,14 +299,9 @@ __host__ __device__ constexpr int pf_bytes() {
 // (P.dbg_tap, P.dbg_line); the production kernels are built without it.
 // PT: StageParams in any address space (a kernel argument, or a descriptor
 // in the constant space read field by field where it is used).
-// PF: the prefetching tile loop (FP64 FP16 full-length tiles, unpacked):
-// the tile's input is already in this thread's LDS slots, and (nctile, ng),
-// when nctile >= 0, is the tile whose input it fetches into them during its
-// epilogue.
 template <int SUB, int TGT, int KMAX, bool FULL = false, bool H0 = false, int NP = 1, bool TAP = false,
-          class PT = StageParams, bool PF = false>
-__device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g, int64_t nctile = -1,
-                                           int64_t ng = 0) {
+          class PT = StageParams>
+__device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g) {
   typedef Tgt<TGT> TT;
   typedef Shape<KMAX> SH;
   typedef StageLds<SUB, TGT, KMAX> LY;
@@ -386,15 +323,6 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   int64_t* col_out = col_in + NCR;
   int* cexp = (int*)(col_out + NCR);
   int* pexp = cexp + NCR;
-  // the plan's constant tables: in the tile loop their addresses are made
-  // opaque per tile, so that the compiler re-reads the constants inside each
-  // tile instead of hoisting them out of the loop into registers
-  const void* mc_p = P.mc;
-  const void* crt_p = P.crt;
-  if (PF) {
-    asm volatile("" : "+s"(mc_p));
-    asm volatile("" : "+s"(crt_p));
-  }
 
   // opaque to the optimiser: a persistent caller must not keep values derived
   // from the thread index live across its loop (they are cheap to recompute)
@@ -443,16 +371,12 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   double ar[KQ], br[KQ];
   int lmax = INT_MIN;
   bool nonfinite = false;
-  static_assert(!PF || (SUB == SUB_FP16 && TGT == 0 && FULL && NP == 1 && !TAP), "prefetch: FP64 FP16 full tiles");
-  if (PF) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's slots have landed
 #pragma unroll
   for (int u = 0; u < KQ; u++) {
     const int s = part * KQ + u - blk * BR;  // index within the column
     double xr = 0.0, xi = 0.0;
     if (cin >= 0 && s < KR) {
-      const typename TT::V2 v =
-          PF ? *(const typename TT::V2*)(smem + pf_offset<SUB, TGT, KMAX>() + (u * kThreads + tid) * 16)
-             : ((const OB_GLOBAL typename TT::V2*)P.in)[cin + (int64_t)s * P.s_in_s];
+      const typename TT::V2 v = ((const OB_GLOBAL typename TT::V2*)P.in)[cin + (int64_t)s * P.s_in_s];
       xr = (double)v.x;
       xi = (double)v.y;
     }
@@ -525,7 +449,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     float rrv[4], riv[4];
     int fm = 0, fb = 0, fc = 0, fn = 0;
     if (H0) {
-      const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)mc_p;
+      const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)P.mc;
       fm = MC.m[i];
       fb = MC.fold_b[i];
       fc = MC.fold_c[i];
@@ -568,7 +492,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
 #pragma unroll
   for (int i = 0; i < R; i++) {
     unsigned char* dig = smem + ((i & 1) ? DIG : 0);  // an offset, not a pointer select
-    const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)mc_p;
+    const OB_CONST ModConsts& MC = *(const OB_CONST ModConsts*)P.mc;
     const double md = MC.md[i], imd = MC.inv_md[i];
     const float mf = MC.mf[i], imf = MC.inv_mf[i];
     // FP8 digits per residue: 3 for the moduli before the split (> 1052),
@@ -789,31 +713,13 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   if (mt_active) combine(R - 1, pD, pE, pF, pmf, pimf);
   if (!mt_active) return;
 
-  if (PF && nctile >= 0) {
-    // the next tile's input into this thread's slots, behind the epilogue
-    // (issued after the last load this tile waits for, before the epilogue's
-    // constants are live)
-    const int64_t cin_n = column_in(P, nctile * NCR + rc, ng);
-    if (cin_n >= 0) {
-#pragma unroll
-      for (int u = 0; u < KQ; u++) {
-        const int sn = part * KQ + u;
-        const OB_GLOBAL typename TT::V2* src = (const OB_GLOBAL typename TT::V2*)P.in + cin_n + (int64_t)sn * P.s_in_s;
-        __builtin_amdgcn_global_load_lds(
-            (const void*)src,
-            (__attribute__((address_space(3))) void*)(smem + pf_offset<SUB, TGT, KMAX>() +
-                                                      (u * kThreads + wave * 64) * 16),
-            16, 0, 0);
-      }
-    }
-  }
   // ---- Phase A (FP16 MFMA) + Phase B (Kulisch, lift, pack) ----
   // Round (v, Re/Im): every lane reconstructs its own output of that row and
   // part.  The low lane half feeds moduli 0 .. ML-1 of its record and the
   // high half moduli ML .. r-1; one swap per packed pair hands each half the
   // other half's share (b1: the low lanes' outputs, b2: the high lanes').
   const v8h aop = *(const OB_GLOBAL v8h*)(P.phaseA + lane * 8);
-  const OB_CONST CrtConsts& C = *(const OB_CONST CrtConsts*)crt_p;
+  const OB_CONST CrtConsts& C = *(const OB_CONST CrtConsts*)P.crt;
   const v16f seed = phase_a_seed(C.seedT_c, lane >> 5);
   const typename EP::LiftK LK = EP::load_lift(C, false);
   // packed: lane l holds rows 4 (l / 16) .. + 3, i.e. column 4 (l / 16) / BR of the group
@@ -915,53 +821,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
   stage_tile<SUB, TGT, KMAX, FULL, H0, NP, TAP>(P, c, g);
 }
 
-// Prefetching tile loop: gridDim.x workgroups (a multiple of 8, so that each
-// keeps its XCD's share of the tile order) walk the tiles vb = blockIdx.x +
-// k gridDim.x; the input of the next tile is fetched into LDS during the
-// current tile's epilogue.  FP64 target, FP16 substrate, full-length
-// unpacked tiles.
-template <int KMAX, bool H0>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_stage_loop_kernel(
-    const StageParams P, int64_t ntiles) {
-  typedef Shape<KMAX> SH;
-  const uint32_t step = gridDim.x;
-  uint32_t vb = blockIdx.x;
-  if (vb >= (uint32_t)ntiles) return;
-  uint32_t c, g;
-  decode_tile32(P, vb, c, g);
-  {
-    // the first tile's input
-    int tid = threadIdx.x;
-    const int jc = tid % SH::NCOL, part = tid / SH::NCOL;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t cin = column_in(P, (int64_t)c * SH::NCOL + jc, g);
-    if (cin >= 0) {
-#pragma unroll
-      for (int u = 0; u < SH::KQ; u++) {
-        const OB_GLOBAL double2* src = (const OB_GLOBAL double2*)P.in + cin + (int64_t)(part * SH::KQ + u) * P.s_in_s;
-        __builtin_amdgcn_global_load_lds(
-            (const void*)src,
-            (__attribute__((address_space(3))) void*)(smem + pf_offset<SUB_FP16, 0, KMAX>() +
-                                                      (u * kThreads + wave * 64) * 16),
-            16, 0, 0);
-      }
-    }
-  }
-  for (;;) {
-    const uint32_t nvb = vb + step;
-    const bool more = nvb < (uint32_t)ntiles;
-    uint32_t nc = 0, ng = 0;
-    if (more) decode_tile32(P, nvb, nc, ng);
-    stage_tile<SUB_FP16, 0, KMAX, true, H0, 1, false, StageParams, true>(P, c, g, more ? (int64_t)nc : -1, ng);
-    if (!more) break;
-    // the next tile rewrites the LDS tables this one's slower waves may still read
-    __syncthreads();
-    vb = nvb;
-    c = nc;
-    g = ng;
-  }
-}
-
 // Batched stage: one workgroup per tile of the members of one Bailey pass
 // whose contraction length falls in this kernel's class.  tmember[t] is the
 // member that owns tile t, descs[d] its stage and first[d] its first tile.
@@ -1000,30 +859,6 @@ static hipError_t launch_stage_t(const StageParams& P, dim3 grid, hipStream_t st
   return hipGetLastError();
 }
 
-// The prefetching tile loop: as many workgroups as the device holds at once
-// (rounded down to a multiple of 8), at most one per tile.
-template <int KMAX, bool H0>
-static hipError_t launch_stage_loop(const StageParams& P, dim3 grid, hipStream_t st) {
-  const int64_t tiles = (int64_t)grid.x * grid.y * grid.z;
-  const int lds = pf_offset<SUB_FP16, 0, KMAX>() + pf_bytes<KMAX>();
-  static int resident = 0;
-  if (!resident) {
-    hipError_t e = hipFuncSetAttribute((const void*)ob_stage_loop_kernel<KMAX, H0>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ob_stage_loop_kernel<KMAX, H0>,
-                                                          kThreads, lds)) != hipSuccess ||
-        (e = hipGetDevice(&dev)) != hipSuccess ||
-        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-      return e;
-    resident = std::max(8, (per_cu * cus) & ~7);
-  }
-  const int64_t wgs = std::min<int64_t>(tiles, resident);
-  hipLaunchKernelGGL((ob_stage_loop_kernel<KMAX, H0>), dim3((unsigned)wgs), dim3(kThreads), lds, st, P, tiles);
-  return hipGetLastError();
-}
-
 // Full-length variants for the default substrate at K = 12, 16 and 32 and
 // the packed tiles for K <= 8 (four columns per tile up to K = 4, two up to
 // K = 8), the full-length FP8 tile at K = 32 when the plan's modulus set
@@ -1048,11 +883,7 @@ static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st
     if (F && K == 16) return launch_stage_t<SUB, TGT, 16, F, H0, TAP>(P, grid, st);
     return launch_stage_t<SUB, TGT, 16, false, H0, TAP>(P, grid, st);
   }
-  if (F && K == 32) {
-    if constexpr (F && TGT == 0 && !TAP)
-      if (P.tile_loop) return launch_stage_loop<32, H0>(P, grid, st);
-    return launch_stage_t<SUB, TGT, 32, F, H0, TAP>(P, grid, st);
-  }
+  if (F && K == 32) return launch_stage_t<SUB, TGT, 32, F, H0, TAP>(P, grid, st);
   if (SUB == SUB_FP8 && K == 32 && P.fp8_full) return launch_stage_t<SUB, TGT, 32, true, H0, TAP>(P, grid, st);
   return launch_stage_t<SUB, TGT, 32, false, H0, TAP>(P, grid, st);
 }

@@ -128,10 +128,7 @@ struct StageParams {
   int64_t dbg_line;         // the tapped line: outer * inner + inner index
   int fp8_full;             // FP8: the modulus set has 3 digits per residue for the moduli
                             // before the split and 2 after it (the full-length tile's rule)
-  int tile_loop;            // run full-length FP16 tiles as the prefetching tile loop
-  // multiply-high divisions of the tile order (stage 2): by tiles_per_g, by
-  // the tiles of one block of the group-minor order (T/8 GB or T GB), by gblock
-  uint32_t T_magic, T_shift, blk_magic, blk_shift, gb_magic, gb_shift;
+  int pad_;
 };
 
 // One output's epilogue record in the debug tap of a stage, as the debug

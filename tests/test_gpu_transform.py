@@ -215,20 +215,3 @@ def test_fp8_general_tile_at_k32(gpu):
     y0 = _run(api.Plan(shape), x, gpu)
     y1 = _run(api.Plan(shape, substrate="fp8", moduli=mods), x, gpu)
     assert np.array_equal(y0, y1)
-
-
-@pytest.mark.parametrize("shape", [(64, 32, 1024), (3, 1024, 40), (1024, 6, 11), (5, 7, 1024)])
-def test_tile_loop_bit_identical(gpu, shape):
-    """The prefetching tile loop (full-length FP16 K = 32 stages: resident
-    workgroups walk the tiles and fetch the next tile's input into LDS during
-    the epilogue) gives the one-workgroup-per-tile launch's bits: several
-    tiles per workgroup, group-major and group-minor stage-2 orders, ragged
-    last tiles; and the oracle's on the smallest."""
-    api = _api()
-    x = inputs.uniform(shape, 15)
-    y0 = _run(api.Plan(shape), x, gpu)
-    y1 = _run(api.Plan(shape, tile_loop=1), x, gpu)
-    assert np.array_equal(y0, y1)
-    if np.prod(shape) <= 40000:
-        plan = api.Plan(shape, tile_loop=1)
-        assert np.count_nonzero(y1 != ox.fft3_exact(x, _pq(plan))) == 0
