@@ -71,6 +71,18 @@ struct StageLds {
 
 // Writes the digit planes of residue v (exact small integer) of column jc,
 // contraction index s, Karatsuba form `form` (0: a~, 1: b~, 2: a~ + b~).
+// Byte offset of K-slot `slot` of column jc in one form's FP8 planes
+// ([chunk][N-tile][lane][8 bytes]: slot kk of a chunk sits in lane
+// (jc % 16) + 16 (kk / 8) at byte kk % 8).
+template <int CHB, int NT>
+__device__ __forceinline__ int fp8_slot(int form, int jc, int slot) {
+  const int ch = slot >> 5, kk = slot & 31;
+  return (((form * CHB + ch) * NT + (jc >> 4)) * 64 + (jc & 15) + 16 * (kk >> 3)) * 8 + (kk & 7);
+}
+
+// FP8 digit slots of index s: three slots 3s .. 3s + 2 for a 3-digit
+// residue (they may straddle lanes and chunks, so bytes are written one by
+// one), two slots 2s, 2s + 1 for a 2-digit one (one 16-bit store).
 template <int SUB, int CHB, int NT>
 __device__ __forceinline__ void put_digits_fp8(unsigned char* dig, int form, int jc, int s, float v, int nd) {
   if (nd == 3) {
@@ -81,49 +93,48 @@ __device__ __forceinline__ void put_digits_fp8(unsigned char* dig, int form, int
     float d1 = __builtin_fmaf(-32.0f, t2, t1);
     uint32_t wd = fp8_pack2<false>(d0, d1, 0u);
     wd = fp8_pack2<true>(t2, 0.0f, wd);
-    int slot = s * 4, ch = slot >> 5, kk = slot & 31;
-    int ln = (jc & 15) + 16 * (kk >> 3);
-    int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
-    *(uint32_t*)(dig + off) = wd;
+#pragma unroll
+    for (int e = 0; e < 3; e++) dig[fp8_slot<CHB, NT>(form, jc, 3 * s + e)] = (unsigned char)(wd >> (8 * e));
   } else {
     float t1 = __builtin_rintf(v * 0.03125f);
     float d0 = __builtin_fmaf(-32.0f, t1, v);
     uint32_t wd = fp8_pack2<false>(d0, t1, 0u);
-    int slot = s * 2, ch = slot >> 5, kk = slot & 31;
-    int ln = (jc & 15) + 16 * (kk >> 3);
-    int off = (((form * CHB + ch) * NT + (jc >> 4)) * 64 + ln) * 8 + (kk & 7);
-    *(uint16_t*)(dig + off) = (uint16_t)wd;
+    *(uint16_t*)(dig + fp8_slot<CHB, NT>(form, jc, 2 * s)) = (uint16_t)wd;
   }
 }
 
 // Full-length FP8 tile: the digits of four consecutive indices s0 .. s0 + 3
-// (s0 % 4 == 0) of column jc in one form, ND digits per index (ND = 3: four
-// slots per index, the fourth zero, so the four indices fill two lanes' 8
-// bytes; ND = 2: two slots per index, one lane's 8 bytes).
+// (s0 % 4 == 0) of column jc in one form.  ND = 3: twelve slots 3 s0 ..
+// 3 s0 + 11, written as three aligned 32-bit words (a 4-byte-aligned word
+// never straddles a lane's 8 bytes or a 32-slot chunk); ND = 2: eight slots,
+// one lane's 8 bytes.
 template <int CHB, int NT, int ND>
 __device__ __forceinline__ void put_digits_fp8_x4(unsigned char* dig, int form, int jc, int s0, const float* v) {
-  uint32_t w[4];
+  float d[4][3];
 #pragma unroll
   for (int u = 0; u < 4; u++) {
     const float t1 = __builtin_rintf(v[u] * 0.03125f);
-    const float d0 = __builtin_fmaf(-32.0f, t1, v[u]);
+    d[u][0] = __builtin_fmaf(-32.0f, t1, v[u]);
     if (ND == 3) {
       const float t2 = __builtin_rintf(t1 * 0.03125f);
-      const float d1 = __builtin_fmaf(-32.0f, t2, t1);
-      w[u] = fp8_pack2<true>(t2, 0.0f, fp8_pack2<false>(d0, d1, 0u));
+      d[u][1] = __builtin_fmaf(-32.0f, t2, t1);
+      d[u][2] = t2;
     } else {
-      w[u] = (u & 1) ? fp8_pack2<true>(d0, t1, w[u - 1]) : fp8_pack2<false>(d0, t1, 0u);
+      d[u][1] = t1;
     }
   }
-  constexpr int NDP = ND == 3 ? 4 : 2;
-  const int slot = s0 * NDP, ch = slot >> 5, kk = slot & 31;
-  const int ln = (jc & 15) + 16 * (kk >> 3);
-  unsigned char* base = dig + ((form * CHB + ch) * NT + (jc >> 4)) * 64 * 8;
   if (ND == 3) {
-    *(uint2*)(base + ln * 8) = make_uint2(w[0], w[1]);
-    *(uint2*)(base + (ln + 16) * 8) = make_uint2(w[2], w[3]);
+    const uint32_t w0 = fp8_pack2<true>(d[0][2], d[1][0], fp8_pack2<false>(d[0][0], d[0][1], 0u));
+    const uint32_t w1 = fp8_pack2<true>(d[2][0], d[2][1], fp8_pack2<false>(d[1][1], d[1][2], 0u));
+    const uint32_t w2 = fp8_pack2<true>(d[3][1], d[3][2], fp8_pack2<false>(d[2][2], d[3][0], 0u));
+    const int b = 3 * s0;
+    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b)) = w0;
+    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b + 4)) = w1;
+    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b + 8)) = w2;
   } else {
-    *(uint2*)(base + ln * 8) = make_uint2(w[1], w[3]);
+    const uint32_t w0 = fp8_pack2<true>(d[1][0], d[1][1], fp8_pack2<false>(d[0][0], d[0][1], 0u));
+    const uint32_t w1 = fp8_pack2<true>(d[3][0], d[3][1], fp8_pack2<false>(d[2][0], d[2][1], 0u));
+    *(uint2*)(dig + fp8_slot<CHB, NT>(form, jc, 2 * s0)) = make_uint2(w0, w1);
   }
 }
 
@@ -360,7 +371,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   // the whole single-slot chunk, for all its columns), so it skips this.
   if (!(FULL && KMAX == 32))
     for (int x = tid * 16; x < 2 * DIG; x += kThreads * 16) *(uint4*)(smem + x) = make_uint4(0, 0, 0, 0);
-  // (the full-length FP8 tile: every modulus writes all 4 or 2 chunks it reads)
+  // (the full-length FP8 tile: every modulus writes all 3 or 2 chunks it reads)
   __syncthreads();
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
@@ -554,14 +565,12 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
           la[u] = i8_limbs(ra);
           lb[u] = i8_limbs(rb);
           ls[u] = i8_limbs(ra + rb);
-        } else {
+        } else if (!FULL) {
           // FP8: digit planes of a~ and b~ (four real products, as FP16)
           ra16[u] = TGT == 1 ? reduce_f32(arf[u], mf, imf) : residue_f64(ar[u], md, imd);
           rb16[u] = TGT == 1 ? reduce_f32(brf[u], mf, imf) : residue_f64(br[u], md, imd);
-          if (!FULL) {
-            put_digits_fp8<SUB, CHB, NT>(dig, 0, jc, s, ra16[u], nd);
-            put_digits_fp8<SUB, CHB, NT>(dig, 1, jc, s, rb16[u], nd);
-          }
+          put_digits_fp8<SUB, CHB, NT>(dig, 0, jc, s, ra16[u], nd);
+          put_digits_fp8<SUB, CHB, NT>(dig, 1, jc, s, rb16[u], nd);
         }
       }
     }
@@ -571,13 +580,17 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
       put_limbs<KQ>(dig + 2 * kI8FormBytes, jc, s0, ls);
     }
     if (SUB == SUB_FP8 && FULL) {
+      // one form at a time: its four residues, then their digits
       static_assert(SUB != SUB_FP8 || !FULL || (KMAX == 32 && KQ == 4), "full-length FP8 tile: K = 32");
-      if (nd == 3) {
-        put_digits_fp8_x4<CHB, NT, 3>(dig, 0, jc, s0, ra16);
-        put_digits_fp8_x4<CHB, NT, 3>(dig, 1, jc, s0, rb16);
-      } else {
-        put_digits_fp8_x4<CHB, NT, 2>(dig, 0, jc, s0, ra16);
-        put_digits_fp8_x4<CHB, NT, 2>(dig, 1, jc, s0, rb16);
+#pragma unroll
+      for (int form = 0; form < 2; form++) {
+        float rv[KQ];
+#pragma unroll
+        for (int u = 0; u < KQ; u++)
+          rv[u] = TGT == 1 ? reduce_f32(form ? brf[u] : arf[u], mf, imf)
+                           : residue_f64(form ? br[u] : ar[u], md, imd);
+        if (nd == 3) put_digits_fp8_x4<CHB, NT, 3>(dig, form, jc, s0, rv);
+        else put_digits_fp8_x4<CHB, NT, 2>(dig, form, jc, s0, rv);
       }
     }
     if (SUB == SUB_FP16 && s0 < K) {
@@ -597,9 +610,9 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     if (SUB == SUB_FP8) {
       // four real products on the digit planes: R = Re A x~ - Im A y~,
       // I = Im A x~ + Re A y~, one accumulator per matrix digit f (every
-      // partial sum is an integer of magnitude <= 2 * 32 * 4 * 16 * 16 <
+      // partial sum is an integer of magnitude <= 2 * 32 * 3 * 16 * 16 <
       // 2^24); R = sum_f 32^f accR[f], |R| < 2^22, exact in FP32
-      const int ndp = nd == 3 ? 4 : 2;
+      const int ndp = nd;  // K slots per index (3 digits: 96 slots, three chunks, at K = 32)
       const int nch = (ndp * K + 31) >> 5;
       v4f accR[3], accI[3];
 #pragma unroll

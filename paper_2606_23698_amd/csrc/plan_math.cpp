@@ -524,7 +524,7 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
       }
       int R = substrate == SUB_INT8 ? 128 : 32;
       int nd = substrate == SUB_INT8 ? 2 : fp8_digits(m);
-      int ndp = substrate == SUB_INT8 ? 2 : (nd == 3 ? 4 : 2);
+      int ndp = substrate == SUB_INT8 ? 2 : nd;  // FP8: nd slots per index
       int nf = nd;
       int pw[3] = {1, R % m, (R * R) % m};
       for (int form = 0; form < 3; form++)
