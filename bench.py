@@ -313,6 +313,69 @@ def cpu_baseline(N, pq, target_s=12.0):
                       f"one {N}^3 transform"}
 
 
+def wide_range_256(api, inputs, steps):
+    """The 256^3 wide-dynamic-range workload (magnitudes 2^u, u uniform in
+    [-20, 20], random signs and phases, seed 1): emulated forward and inverse,
+    the native FP64 forward on the same data, and the round-trip error."""
+    import torch
+    shape = (256, 256, 256)
+    x = torch.from_numpy(inputs.wide_range(shape, 1)).to("cuda:0")
+    plan = api.Plan(shape)
+    y, back, yn = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    ms_f, _ = time_steps(lambda: plan.forward(x, y), steps, 2)
+    ms_i, _ = time_steps(lambda: plan.inverse(y, back), steps, 2)
+    ms_n, _ = time_steps(lambda: plan.native_forward(x, yn), steps, 2)
+    rt = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+    diff = float(torch.linalg.vector_norm(y - yn) / torch.linalg.vector_norm(yn))
+    print(f"[bench] wide-range 256^3: forward {ms_f:.3f} ms, inverse {ms_i:.3f} ms, native {ms_n:.3f} ms, "
+          f"round trip {rt:.2e}", file=sys.stderr, flush=True)
+    out = {"workload": "forward + inverse complex FP64 3-D FFT 256^3, magnitudes 2^u (u uniform[-20,20]), "
+                       "random signs and phases (seed 1)",
+           "forward_ms": round(ms_f, 4), "inverse_ms": round(ms_i, 4), "native_forward_ms": round(ms_n, 4),
+           "hbm_roof_ms": round(96.0 * x.numel() / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+           "rel_l2_round_trip": rt, "rel_l2_emulated_vs_native": diff}
+    del x, y, back, yn
+    torch.cuda.empty_cache()
+    return out
+
+
+def spectral_loss_512(api, inputs, steps):
+    """The differentiable spectral loss L(x) = sum |w_k FFT3(x)|^2, w_k =
+    1 / (1 + |k|^2), at 512^3 (uniform[-1, 1), seed 4): one forward and
+    backward through the autograd function (emulated forward, hand-written
+    adjoint), beside the same gradient from two native FP64 transforms."""
+    import torch
+    from paper_2606_23698_amd import autograd as ag
+    shape = (512, 512, 512)
+    x = inputs.uniform_to_device(shape, 4, device="cuda:0").requires_grad_(True)
+    w = ag.spectral_weights(shape, x.device)
+    plan = api.get_plan(shape, "fp64", "auto", 0)
+
+    def emulated():
+        x.grad = None
+        ag.spectral_loss(x, w).backward()
+
+    def native():
+        with torch.no_grad():
+            yn = plan.native_forward(x.detach())
+            yn.mul_(w * w)
+            return torch.conj(plan.native_forward(torch.conj(yn).resolve_conj())).resolve_conj().mul_(2.0)
+
+    ms_e, _ = time_steps(emulated, steps, 1)
+    ms_n, _ = time_steps(native, steps, 1)
+    ref = native()
+    err = float(torch.linalg.vector_norm(x.grad - ref) / torch.linalg.vector_norm(ref))
+    print(f"[bench] spectral loss 512^3: forward+backward {ms_e:.2f} ms (native gradient {ms_n:.2f} ms), "
+          f"gradient vs native {err:.2e}", file=sys.stderr, flush=True)
+    out = {"workload": "L(x) = sum |w_k FFT3(x)|^2, w_k = 1/(1+|k|^2), complex FP64 512^3 uniform[-1,1) "
+                       "(seed 4): loss and gradient through the autograd function",
+           "forward_backward_ms": round(ms_e, 3), "native_gradient_ms": round(ms_n, 3),
+           "rel_l2_gradient_vs_native": err}
+    del x, w, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +390,8 @@ def main():
     ap.add_argument("--no-native", action="store_true", help="skip the native FP64 comparator")
     ap.add_argument("--no-sweep", action="store_true", help="skip the FP8 / INT8 / FP32-target sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-transform batched measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 256^3 wide-range round trip and the 512^3 spectral-loss gradient")
     ap.add_argument("--no-crt", action="store_true", help="skip the reconstruction-method comparison")
     ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU share of the 8-GPU slab decomposition")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -412,6 +477,10 @@ def main():
         "hbm_roof_ms": round(roof_ms, 3),
         "hbm_roof_frac": round(roof_ms / ms, 4),
         "native_hbm_roof_frac": round(roof_ms / ms_nat, 4) if ms_nat == ms_nat else None,
+        # the roof at the bytes the two-launch axis passes move (Y' leaves the
+        # chip between the stages: 192 B per element per transform)
+        "hbm_roof_moved_ms": round(2.0 * roof_ms, 3),
+        "hbm_roof_moved_frac": round(2.0 * roof_ms / ms, 4),
         "copy_GBs": round(copy_gbs, 1),
         "copy_roof_ms": round(copy_roof_ms, 3),
         "copy_roof_frac": round(copy_roof_ms / ms, 4),
@@ -452,10 +521,14 @@ def main():
         print(f"[bench] error vs double-double on {len(samples)} lines: emulated {err['emulated']:.3e}, "
               f"native {err.get('native_fp64', float('nan')):.3e}, fp32 target "
               f"{acc.get('rel_l2_fp32_target', float('nan')):.3e}", file=sys.stderr, flush=True)
+    # the 1024^3 arrays are not needed after this point
+    del x, y
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del x, y
-        torch.cuda.empty_cache()
         line["batch64"] = batch_throughput(api, inputs, max(2, min(args.steps, 5)))
+    if not args.no_configs:
+        line["wide_range_256"] = wide_range_256(api, inputs, max(3, min(args.steps, 10)))
+        line["spectral_loss_512"] = spectral_loss_512(api, inputs, max(2, min(args.steps, 3)))
     if not args.no_crt:
         line["crt_methods"] = crt_methods(api, inputs, max(5, min(args.steps, 10)))
     if not args.no_slab and N == 1024:
