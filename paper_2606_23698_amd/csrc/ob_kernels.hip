@@ -81,8 +81,9 @@ static hipError_t launch_batch_s(int kmax, bool full, const StageParams* descs, 
                        : launch_batch_t<SUB, 16, false>(descs, first, tmember, total, st);
     default:
       // FP8: `full` also says that the modulus set follows the full-length tile's digit rule
-      return (F || SUB == SUB_FP8) && full ? launch_batch_t<SUB, 32, true>(descs, first, tmember, total, st)
-                                           : launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
+      if constexpr (F || SUB == SUB_FP8)
+        if (full) return launch_batch_t<SUB, 32, true>(descs, first, tmember, total, st);
+      return launch_batch_t<SUB, 32, false>(descs, first, tmember, total, st);
   }
 }
 

@@ -827,7 +827,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
 }
 
 template <int SUB, int TGT, int KMAX, bool FULL, bool H0, int NP, bool TAP>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_stage_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_stage_kernel(
     const StageParams P) {
   int64_t c, g;
   grid_tile(P, c, g);
@@ -838,7 +838,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB ==
 // whose contraction length falls in this kernel's class.  tmember[t] is the
 // member that owns tile t, descs[d] its stage and first[d] its first tile.
 template <int SUB, int TGT, int KMAX, bool FULL, int NP>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SUB == SUB_INT8 ? 1 : 4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void ob_batch_kernel(const StageParams* __restrict__ descs,
                                                             const int64_t* __restrict__ first,
                                                             const uint16_t* __restrict__ tmember, int64_t total) {
   const int64_t t = blockIdx.x;
@@ -897,7 +897,8 @@ static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st
     return launch_stage_t<SUB, TGT, 16, false, H0, TAP>(P, grid, st);
   }
   if (F && K == 32) return launch_stage_t<SUB, TGT, 32, F, H0, TAP>(P, grid, st);
-  if (SUB == SUB_FP8 && K == 32 && P.fp8_full) return launch_stage_t<SUB, TGT, 32, true, H0, TAP>(P, grid, st);
+  if constexpr (SUB == SUB_FP8)
+    if (K == 32 && P.fp8_full) return launch_stage_t<SUB, TGT, 32, true, H0, TAP>(P, grid, st);
   return launch_stage_t<SUB, TGT, 32, false, H0, TAP>(P, grid, st);
 }
 
