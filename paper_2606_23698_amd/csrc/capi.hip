@@ -254,8 +254,20 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
         obfft_status_t s = upload(plan, bytes.data(), bytes.size(), &dptr);
         if (s != OBFFT_SUCCESS) return s;
         L.dev = (uint8_t*)dptr;
+        L.dev128 = nullptr;
         if (sub == SUB_FP8) {
           if (launch_digits_to_fp8(L.dev, (int64_t)bytes.size(), 0) != hipSuccess) return OBFFT_HIP_ERROR;
+          // K = 32 with the full-length digit rule: also the full tile's layout
+          const int64_t K = st == 1 ? plan->q[a] : plan->p[a];
+          if (K == 32 && plan->fp8_full) {
+            OperandPlanes L2;
+            build_operand_planes(plan->H, plan->roots[a], plan->n[a], plan->p[a], plan->q[a], st, d, sub,
+                                 fp16_split, bytes, L2, 1);
+            if (L2.mod_stride != L.mod_stride || L2.g_stride != L.g_stride) return OBFFT_HIP_ERROR;
+            if ((s = upload(plan, bytes.data(), bytes.size(), &dptr)) != OBFFT_SUCCESS) return s;
+            L.dev128 = (uint8_t*)dptr;
+            if (launch_digits_to_fp8(L.dev128, (int64_t)bytes.size(), 0) != hipSuccess) return OBFFT_HIP_ERROR;
+          }
         }
         cache[key] = L;
         plan->planes[a][st - 1][d].L = L;
@@ -473,6 +485,7 @@ static void stage_params(obfft_plan_t plan, int axis, int stage, int direction, 
   P.stage = stage;
   const OperandPlanes& L = plan->planes[axis][stage - 1][direction].L;
   P.amat = L.dev;
+  P.amat128 = L.dev128;
   P.amat_g_stride = stage == 1 ? 0 : L.g_stride;
   P.amat_mod_stride = L.mod_stride;
   P.amat_fmax = L.fmax;

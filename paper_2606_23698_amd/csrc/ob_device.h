@@ -10,6 +10,7 @@ namespace obfft {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));
@@ -54,6 +55,11 @@ __device__ __forceinline__ float fold_reduce_f32(float x, int m, int b, int c, i
 // ---- MFMA wrappers ----
 __device__ __forceinline__ v4f mfma_fp8(long a, long b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+// Scaled 16 x 16 x 128 FP8 (E4M3 x E4M3) MFMA: lane group h's 32-byte block
+// of A is multiplied by 2^(sa - 127); B unscaled.
+__device__ __forceinline__ v4f mfma_fp8_k128(v8i a, v8i b, v4f c, int sa) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, 0, 127);
 }
 __device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);

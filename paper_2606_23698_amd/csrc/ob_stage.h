@@ -138,6 +138,30 @@ __device__ __forceinline__ void put_digits_fp8_x4(unsigned char* dig, int form, 
   }
 }
 
+// Full-length FP8 tile on the scaled K = 128 MFMA: data digit e of indices
+// s0 .. s0 + 3 (s0 % 4 == 0) of column jc in one form, one aligned word per
+// digit, in planes [form][e][N-tile][column][32 indices].
+template <int NT, int ND>
+__device__ __forceinline__ void put_digits_fp8_k128(unsigned char* dig, int form, int jc, int s0, const float* v) {
+  float d[3][4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const float t1 = __builtin_rintf(v[u] * 0.03125f);
+    d[0][u] = __builtin_fmaf(-32.0f, t1, v[u]);
+    if (ND == 3) {
+      const float t2 = __builtin_rintf(t1 * 0.03125f);
+      d[1][u] = __builtin_fmaf(-32.0f, t2, t1);
+      d[2][u] = t2;
+    } else {
+      d[1][u] = t1;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < ND; e++)
+    *(uint32_t*)(dig + ((form * 3 + e) * NT + (jc >> 4)) * 512 + (jc & 15) * 32 + s0) =
+        fp8_pack2<true>(d[e][2], d[e][3], fp8_pack2<false>(d[e][0], d[e][1], 0u));
+}
+
 // INT8 limbs of a residue v (|v| <= 2043): v = d0 + 128 d1 with the low limb
 // d0 = v mod 128 in [0, 127] and the high limb d1 = floor(v / 128) in
 // [-16, 15], both valid signed bytes.  Returns the 16-bit pair (d0 | d1 << 8).
@@ -429,7 +453,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   // A batched launch may run a K <= 16 stage on the two-M-tile shape: the
   // second M-tile then has no rows and no matrix planes.
   const bool mt_active = 16 * mt < K;
-  const uint8_t* amat = P.amat + g * P.amat_g_stride;
+  const uint8_t* amat = ((SUB == SUB_FP8 && FULL) ? P.amat128 : P.amat) + g * P.amat_g_stride;
   const int col = nt * 16 + (lane & 15);
   // INT8 planes: [form][N-tile][lane][16 bytes]; contraction index s of
   // column jc sits in lane (jc % 16) + 16 (s / 8) at byte 2 (s % 8).
@@ -589,8 +613,8 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
         for (int u = 0; u < KQ; u++)
           rv[u] = TGT == 1 ? reduce_f32(form ? brf[u] : arf[u], mf, imf)
                            : residue_f64(form ? br[u] : ar[u], md, imd);
-        if (nd == 3) put_digits_fp8_x4<CHB, NT, 3>(dig, form, jc, s0, rv);
-        else put_digits_fp8_x4<CHB, NT, 2>(dig, form, jc, s0, rv);
+        if (nd == 3) put_digits_fp8_k128<NT, 3>(dig, form, jc, s0, rv);
+        else put_digits_fp8_k128<NT, 2>(dig, form, jc, s0, rv);
       }
     }
     if (SUB == SUB_FP16 && s0 < K) {
@@ -621,32 +645,48 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
         accI[f] = (v4f){0.f, 0.f, 0.f, 0.f};
       }
       if (FULL) {
-        // every chunk's A digit planes (Re A, Im A, -Im A x nd digits) are
-        // issued together through the buffer resource, then its 4 nd MFMAs
+        // the scaled 16 x 16 x 128 MFMA: the nd^2 (matrix digit f, data digit
+        // e) blocks of 32 slots, four per instruction (block b holds bytes
+        // 16 (b / 2) .. + 15 of lane groups 2 (b % 2), 2 (b % 2) + 1); lane
+        // group h scales its block of A by 32^f, so that one accumulator
+        // takes sum_f 32^f (digit-f sum).  Every partial sum is an integer of
+        // magnitude <= 2 * 32 * 3 * 16 * (16 + 32 * 16 + 1024) < 2^23: exact.
+        const int h = lane >> 4;
+        const int nins = nd == 3 ? 3 : 1;
 #pragma unroll
-        for (int ch = 0; ch < 4; ch++) {
-          if (ch < nch) {
-            const long bx = *(const long*)(dig + (((0 * CHB + ch) * NT + nt) * 64 + lane) * 8);
-            const long by = *(const long*)(dig + (((1 * CHB + ch) * NT + nt) * 64 + lane) * 8);
-            long a8[3][3];
+        for (int ins = 0; ins < 3; ins++) {
+          if (ins < nins) {
+            v8i bx, by;
 #pragma unroll
-            for (int pl = 0; pl < 3; pl++)
-#pragma unroll
-              for (int f = 0; f < 3; f++)
-                if (f < nd)
-                  a8[pl][f] = __builtin_bit_cast(
-                      long, __builtin_amdgcn_raw_buffer_load_b64(
-                                arsrc, (uint32_t)lane * 8u,
-                                (uint32_t)(i * P.amat_mod_stride + (((pl * 3 + f) * 2 + mt) * 4 + ch) * 512), 0));
-#pragma unroll
-            for (int f = 0; f < 3; f++) {
-              if (f < nd) {
-                accR[f] = mfma_fp8(a8[0][f], bx, accR[f]);
-                accI[f] = mfma_fp8(a8[1][f], bx, accI[f]);
-                accR[f] = mfma_fp8(a8[2][f], by, accR[f]);
-                accI[f] = mfma_fp8(a8[0][f], by, accI[f]);
-              }
+            for (int pc = 0; pc < 2; pc++) {
+              const int b = pc ? 2 + (h >> 1) : (h >> 1);
+              const int idx = 4 * ins + b;
+              const int e = idx < nd * nd ? idx % nd : 0;
+              const int off = (e * NT + nt) * 512 + (lane & 15) * 32 + 16 * (h & 1);
+              const uint4 wx = *(const uint4*)(dig + off);
+              const uint4 wy = *(const uint4*)(dig + 3 * NT * 512 + off);
+              bx[4 * pc] = wx.x; bx[4 * pc + 1] = wx.y; bx[4 * pc + 2] = wx.z; bx[4 * pc + 3] = wx.w;
+              by[4 * pc] = wy.x; by[4 * pc + 1] = wy.y; by[4 * pc + 2] = wy.z; by[4 * pc + 3] = wy.w;
             }
+            const int idxa = 4 * ins + h;
+            const int sa = 127 + 5 * (idxa < nd * nd ? idxa / nd : 0);
+            // the last instruction of a 3-digit modulus holds one block: only
+            // the first 16 bytes of its A lanes can be non-zero
+            const bool half = nd == 3 && ins == 2;
+            // one A plane at a time: Re A (x and y), Im A (x), -Im A (y)
+            auto aplane = [&](int pl) {
+              const uint32_t so = (uint32_t)(i * P.amat_mod_stride + ((pl * 3 + ins) * 2 + mt) * 2048);
+              const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(arsrc, (uint32_t)lane * 32u, so, 0));
+              const v4i hi = half ? (v4i){0, 0, 0, 0}
+                                  : __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                arsrc, (uint32_t)lane * 32u + 16u, so, 0));
+              return (v8i){lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            };
+            const v8i are = aplane(0);
+            accR[0] = mfma_fp8_k128(are, bx, accR[0], sa);
+            accI[0] = mfma_fp8_k128(are, by, accI[0], sa);
+            accI[0] = mfma_fp8_k128(aplane(1), bx, accI[0], sa);
+            accR[0] = mfma_fp8_k128(aplane(2), by, accR[0], sa);
           }
         }
       } else {
@@ -669,9 +709,9 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
       }
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        Dv[v] = __builtin_fmaf(1024.0f, accR[2][v], __builtin_fmaf(32.0f, accR[1][v], accR[0][v]));
+        Dv[v] = FULL ? accR[0][v] : __builtin_fmaf(1024.0f, accR[2][v], __builtin_fmaf(32.0f, accR[1][v], accR[0][v]));
         Ev[v] = 0.0f;
-        Fv[v] = __builtin_fmaf(1024.0f, accI[2][v], __builtin_fmaf(32.0f, accI[1][v], accI[0][v]));
+        Fv[v] = FULL ? accI[0][v] : __builtin_fmaf(1024.0f, accI[2][v], __builtin_fmaf(32.0f, accI[1][v], accI[0][v]));
       }
     } else if (SUB == SUB_FP16) {
       // four real products, accumulated exactly in FP32 (every partial sum

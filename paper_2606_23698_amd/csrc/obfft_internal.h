@@ -115,6 +115,7 @@ struct StageParams {
                                                         // for n < 2^31 (magic 0: d = 1)
   int extra_shift;      // added to the pack exponent
   const uint8_t* amat;  // MFMA A-operand planes of this stage / direction
+  const uint8_t* amat128;  // the full-length FP8 tile's planes (same strides), or null
   int64_t amat_g_stride;  // bytes per group g (0 for stage 1)
   int amat_fmax, amat_chmax, amat_mt;  // layout extents of the planes
   int64_t amat_bytes;                  // bytes of the planes from amat on (all groups)
@@ -175,6 +176,8 @@ constexpr unsigned kPersistMaskAll = (1u << kPersistVariants) - 1;
 // Plan-time per-(N, p, q) operand set for one stage direction.
 struct OperandPlanes {
   uint8_t* dev;          // device copy
+  uint8_t* dev128;       // FP8, K = 32, full-length tile: the same planes laid out for the
+                         // scaled K = 128 MFMA (null otherwise)
   int64_t g_stride;      // bytes per group
   int64_t mod_stride;    // bytes per modulus
   int fmax, chmax, mt;

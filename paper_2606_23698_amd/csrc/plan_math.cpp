@@ -456,8 +456,11 @@ void h0_fold_form(int m, int* b, int* c, int* nf) {
 
 void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
                           int64_t p, int64_t q, int stage, int direction, int substrate,
-                          int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L) {
+                          int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L, int layout128) {
   int K = stage == 1 ? (int)q : (int)p;
+  // layout128: the planes of the full-length FP8 tile (K = 32) on the scaled
+  // K = 128 MFMA instead of the general tile's
+  const bool k128 = substrate == SUB_FP8 && K == 32 && layout128;
   int G = stage == 1 ? 1 : (int)q;
   // packed FP16 tiles: the planes are the block-diagonal diag(F, ..., F) of
   // np blocks of 16 / np rows and slots in a 16 x 16 matrix
@@ -519,6 +522,37 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
                                 (((int64_t)form * MT + mt) * chmax + ch) * chunk_bytes + lane * bpl + 2 * j;
                   bytes[off] = (uint8_t)(h & 0xFF);
                   bytes[off + 1] = (uint8_t)(h >> 8);
+                }
+        continue;
+      }
+      if (k128) {
+        // Full-length FP8 tile on the scaled 16 x 16 x 128 MFMA: the
+        // products (matrix digit f, data digit e) of one modulus form nd^2
+        // blocks of 32 slots (index s), taken four to an instruction in the
+        // order idx = f nd + e; block b of an instruction sits at bytes
+        // 16 (b / 2) .. + 15 of lane groups 2 (b % 2) and 2 (b % 2) + 1, the
+        // first 16 indices in the first group.  [form][instr][M-tile][lane][32 bytes].
+        const int nd = fp8_digits(m);
+        const int pw[3] = {1, 32 % m, (32 * 32) % m};
+        for (int form = 0; form < 3; form++)
+          for (int ins = 0; ins < 3; ins++)
+            for (int mt = 0; mt < MT; mt++)
+              for (int lane = 0; lane < 64; lane++)
+                for (int j = 0; j < 32; j++) {
+                  const int h = lane / 16, t = 16 * mt + lane % 16;
+                  const int b = j < 16 ? h / 2 : 2 + h / 2;
+                  const int idx = 4 * ins + b;
+                  const int s = 16 * (h % 2) + j % 16;
+                  int digit = 0;
+                  if (idx < nd * nd && t < K && s < K) {
+                    const int f = idx / nd, e = idx % nd;
+                    int d[3];
+                    balanced_digits(centred((int64_t)cval[(form * K + t) * K + s] * pw[e], m), 32, nd, d);
+                    digit = d[f];
+                  }
+                  const int64_t off = g * L.g_stride + i * L.mod_stride +
+                                      (((int64_t)form * 3 + ins) * MT + mt) * 2048 + lane * 32 + j;
+                  bytes[off] = (uint8_t)(int8_t)digit;
                 }
         continue;
       }

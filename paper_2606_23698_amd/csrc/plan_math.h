@@ -38,7 +38,7 @@ uint8_t e4m3_encode(int d);
 uint16_t f16_encode_int(int v);
 void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, int64_t N,
                           int64_t p, int64_t q, int stage, int direction, int substrate,
-                          int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L);
+                          int fp16_split, std::vector<uint8_t>& bytes, OperandPlanes& L, int layout128 = 0);
 // True when residues mod m may enter the FP16 residue GEMM as one slot per
 // index (no limb split) with an exact FP32 accumulation.
 bool fp16_single_slot_ok(int m);

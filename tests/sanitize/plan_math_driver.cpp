@@ -47,6 +47,9 @@ int main() {
             OperandPlanes L;
             build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, prec ? 3 : 4, bytes, L);
             for (uint8_t b : bytes) sum = sum * 31 + b;
+            // the full-length FP8 tile's layout (K = 32 stages)
+            build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, prec ? 3 : 4, bytes, L, 1);
+            for (uint8_t b : bytes) sum = sum * 31 + b;
           }
     }
   }
