@@ -56,7 +56,7 @@ struct Shape {
 // a~ + b~), FP16 and FP8 the two forms (a~, b~) of the four-product complex
 // GEMM.
 __host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
-  return (sub == SUB_INT8 ? 3 : 2) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
+  return (sub == SUB_FP16 ? 2 : 3) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
 }
 
 // LDS of one workgroup: two digit buffers (even / odd moduli), the column
@@ -140,8 +140,9 @@ __device__ __forceinline__ void put_digits_fp8_x4(unsigned char* dig, int form, 
 
 // Full-length FP8 tile on the scaled K = 128 MFMA: data digit e of indices
 // s0 .. s0 + 3 (s0 % 4 == 0) of column jc in one form, one aligned word per
-// digit, in planes [form][e][N-tile][column][32 indices].
-template <int NT, int ND>
+// digit, in planes [form][e][N-tile][column][32 indices]; NEG: also the
+// negated digits (E4M3 sign bits flipped) as form + 1.
+template <int NT, int ND, bool NEG = false>
 __device__ __forceinline__ void put_digits_fp8_k128(unsigned char* dig, int form, int jc, int s0, const float* v) {
   float d[3][4];
 #pragma unroll
@@ -157,9 +158,11 @@ __device__ __forceinline__ void put_digits_fp8_k128(unsigned char* dig, int form
     }
   }
 #pragma unroll
-  for (int e = 0; e < ND; e++)
-    *(uint32_t*)(dig + ((form * 3 + e) * NT + (jc >> 4)) * 512 + (jc & 15) * 32 + s0) =
-        fp8_pack2<true>(d[e][2], d[e][3], fp8_pack2<false>(d[e][0], d[e][1], 0u));
+  for (int e = 0; e < ND; e++) {
+    const uint32_t w = fp8_pack2<true>(d[e][2], d[e][3], fp8_pack2<false>(d[e][0], d[e][1], 0u));
+    *(uint32_t*)(dig + ((form * 3 + e) * NT + (jc >> 4)) * 512 + (jc & 15) * 32 + s0) = w;
+    if (NEG) *(uint32_t*)(dig + (((form + 1) * 3 + e) * NT + (jc >> 4)) * 512 + (jc & 15) * 32 + s0) = w ^ 0x80808080u;
+  }
 }
 
 // INT8 limbs of a residue v (|v| <= 2043): v = d0 + 128 d1 with the low limb
@@ -613,8 +616,14 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
         for (int u = 0; u < KQ; u++)
           rv[u] = TGT == 1 ? reduce_f32(form ? brf[u] : arf[u], mf, imf)
                            : residue_f64(form ? br[u] : ar[u], md, imd);
-        if (nd == 3) put_digits_fp8_k128<NT, 3>(dig, form, jc, s0, rv);
-        else put_digits_fp8_k128<NT, 2>(dig, form, jc, s0, rv);
+        // form 1 (b~) also as -b~ (form 2), so that the real part takes Im A x (-b~)
+        if (nd == 3) {
+          if (form) put_digits_fp8_k128<NT, 3, true>(dig, form, jc, s0, rv);
+          else put_digits_fp8_k128<NT, 3>(dig, form, jc, s0, rv);
+        } else {
+          if (form) put_digits_fp8_k128<NT, 2, true>(dig, form, jc, s0, rv);
+          else put_digits_fp8_k128<NT, 2>(dig, form, jc, s0, rv);
+        }
       }
     }
     if (SUB == SUB_FP16 && s0 < K) {
@@ -656,24 +665,27 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
 #pragma unroll
         for (int ins = 0; ins < 3; ins++) {
           if (ins < nins) {
-            v8i bx, by;
+            // this lane group's two blocks of data digits of one form (a~, b~, -b~)
+            auto bplane = [&](int form) {
+              v8i bv;
 #pragma unroll
-            for (int pc = 0; pc < 2; pc++) {
-              const int b = pc ? 2 + (h >> 1) : (h >> 1);
-              const int idx = 4 * ins + b;
-              const int e = idx < nd * nd ? idx % nd : 0;
-              const int off = (e * NT + nt) * 512 + (lane & 15) * 32 + 16 * (h & 1);
-              const uint4 wx = *(const uint4*)(dig + off);
-              const uint4 wy = *(const uint4*)(dig + 3 * NT * 512 + off);
-              bx[4 * pc] = wx.x; bx[4 * pc + 1] = wx.y; bx[4 * pc + 2] = wx.z; bx[4 * pc + 3] = wx.w;
-              by[4 * pc] = wy.x; by[4 * pc + 1] = wy.y; by[4 * pc + 2] = wy.z; by[4 * pc + 3] = wy.w;
-            }
+              for (int pc = 0; pc < 2; pc++) {
+                const int b = pc ? 2 + (h >> 1) : (h >> 1);
+                const int idx = 4 * ins + b;
+                const int e = idx < nd * nd ? idx % nd : 0;
+                const uint4 w = *(const uint4*)(dig + ((form * 3 + e) * NT + nt) * 512 + (lane & 15) * 32 + 16 * (h & 1));
+                bv[4 * pc] = w.x;
+                bv[4 * pc + 1] = w.y;
+                bv[4 * pc + 2] = w.z;
+                bv[4 * pc + 3] = w.w;
+              }
+              return bv;
+            };
             const int idxa = 4 * ins + h;
             const int sa = 127 + 5 * (idxa < nd * nd ? idxa / nd : 0);
             // the last instruction of a 3-digit modulus holds one block: only
             // the first 16 bytes of its A lanes can be non-zero
             const bool half = nd == 3 && ins == 2;
-            // one A plane at a time: Re A (x and y), Im A (x), -Im A (y)
             auto aplane = [&](int pl) {
               const uint32_t so = (uint32_t)(i * P.amat_mod_stride + ((pl * 3 + ins) * 2 + mt) * 2048);
               const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(arsrc, (uint32_t)lane * 32u, so, 0));
@@ -682,11 +694,14 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
                                                                 arsrc, (uint32_t)lane * 32u + 16u, so, 0));
               return (v8i){lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
             };
+            // R = Re A x~ + Im A (-y~), I = Im A x~ + Re A y~
+            const v8i bx = bplane(0);
             const v8i are = aplane(0);
             accR[0] = mfma_fp8_k128(are, bx, accR[0], sa);
-            accI[0] = mfma_fp8_k128(are, by, accI[0], sa);
-            accI[0] = mfma_fp8_k128(aplane(1), bx, accI[0], sa);
-            accR[0] = mfma_fp8_k128(aplane(2), by, accR[0], sa);
+            accI[0] = mfma_fp8_k128(are, bplane(1), accI[0], sa);
+            const v8i aim = aplane(1);
+            accI[0] = mfma_fp8_k128(aim, bx, accI[0], sa);
+            accR[0] = mfma_fp8_k128(aim, bplane(2), accR[0], sa);
           }
         }
       } else {

@@ -531,10 +531,11 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
         // blocks of 32 slots (index s), taken four to an instruction in the
         // order idx = f nd + e; block b of an instruction sits at bytes
         // 16 (b / 2) .. + 15 of lane groups 2 (b % 2) and 2 (b % 2) + 1, the
-        // first 16 indices in the first group.  [form][instr][M-tile][lane][32 bytes].
+        // first 16 indices in the first group.  [form][instr][M-tile][lane][32 bytes];
+        // forms Re A and Im A only (the kernel negates the data instead of Im A).
         const int nd = fp8_digits(m);
         const int pw[3] = {1, 32 % m, (32 * 32) % m};
-        for (int form = 0; form < 3; form++)
+        for (int form = 0; form < 2; form++)
           for (int ins = 0; ins < 3; ins++)
             for (int mt = 0; mt < MT; mt++)
               for (int lane = 0; lane < 64; lane++)
