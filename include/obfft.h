@@ -294,7 +294,8 @@ void obfft_taps_layout(obfft_taps_layout_t* layout);
  * 16 float); 3: permlane32 swap (a, b: 64 uint32, d: 2 x 64 uint32); 4: E4M3
  * conversion of 64 floats in a (b unused) into 64 bytes of d; 5: FP16
  * 16x16x32 (64 x 8 half, d: 64 x 4 float); 6: INT8 32x32x32 (64 x 16 bytes,
- * d: 64 x 16 int32). */
+ * d: 64 x 16 int32); 7: scaled FP8 16x16x128 (a: 64 x 32 bytes followed by
+ * 64 int32 E8M0 scales of A, b: 64 x 32 bytes unscaled, d: 64 x 4 float). */
 obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream);
 
 /* Host-only introspection (no device needed). */

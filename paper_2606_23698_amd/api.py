@@ -365,12 +365,13 @@ def taps_layout():
 
 # bytes of (a and b, d) of each probe kind (one register set per lane, 64 lanes)
 _PROBE_BYTES = {0: (512, 1024), 1: (1024, 1024), 2: (1024, 4096), 3: (256, 512), 4: (256, 64),
-                5: (1024, 1024), 6: (1024, 4096)}
+                5: (1024, 1024), 6: (1024, 4096), 7: (2048, 1024)}
 
 
 def mfma_probe(kind, a, b, d, stream=None):
     need_ab, need_d = _PROBE_BYTES[kind]
-    for name, t, need in (("a", a, need_ab), ("b", b, need_ab if kind != 4 else 0), ("d", d, need_d)):
+    need_a = need_ab + (256 if kind == 7 else 0)  # kind 7: 64 scales after the operands
+    for name, t, need in (("a", a, need_a), ("b", b, need_ab if kind != 4 else 0), ("d", d, need_d)):
         if t is None and need == 0:
             continue
         if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or \

@@ -849,7 +849,7 @@ extern "C" void obfft_taps_layout(obfft_taps_layout_t* t) {
 // the hardware-contract tests.  kind: 0 fp8 16x16x32, 1 i8 16x16x64,
 // 2 f16 32x32x16, 3 permlane32 swap, 4 E4M3 conversion, 5 f16 16x16x32.
 extern "C" obfft_status_t obfft_mfma_probe(int kind, const void* a, const void* b, void* d, void* stream) {
-  if (kind < 0 || kind > 6 || !a || !d || (kind != 4 && !b)) return OBFFT_INVALID_VALUE;
+  if (kind < 0 || kind > 7 || !a || !d || (kind != 4 && !b)) return OBFFT_INVALID_VALUE;
   if (!device_is_gfx950()) return OBFFT_UNSUPPORTED_DEVICE;
   return launch_mfma_probe(kind, a, b, d, (hipStream_t)stream) == hipSuccess ? OBFFT_SUCCESS : OBFFT_HIP_ERROR;
 }

@@ -37,6 +37,13 @@ __global__ void mfma_probe_kernel(int kind, const void* a, const void* b, void* 
     v16i_t c;
     for (int v = 0; v < 16; v++) c[v] = 0;
     ((v16i_t*)d)[lane] = mfma_i8_32(av, bv, c);
+  } else if (kind == 7) {
+    // scaled K = 128 FP8 MFMA: a = 64 lanes x 32 bytes, then 64 E8M0 scales of A (one int each);
+    // b = 64 lanes x 32 bytes (unscaled)
+    const v8i av = ((const v8i*)a)[lane], bv = ((const v8i*)b)[lane];
+    const int sa = ((const int*)a)[64 * 8 + lane];
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    ((v4f*)d)[lane] = mfma_fp8_k128(av, bv, c, sa);
   } else if (kind == 4) {
     // E4M3 conversion of small integers: a = 64 floats, d = 64 bytes
     float x = ((const float*)a)[lane];

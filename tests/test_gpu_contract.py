@@ -49,6 +49,54 @@ def test_fp8_mfma_16x16x32_layout_and_exactness(gpu):
         assert np.array_equal(got, ref)
 
 
+def _k128_slot(h, j):
+    """K index of byte j of lane group h in the scaled 16 x 16 x 128 FP8 MFMA."""
+    return 16 * h + j if j < 16 else 64 + 16 * h + (j - 16)
+
+
+@pytest.mark.parametrize("trial", ["random", "digit_weights"])
+def test_fp8_scaled_mfma_16x16x128_layout_and_scales(gpu, trial):
+    """The full-length FP8 tile's contract: lane l holds row (column) l % 16
+    and bytes of K indices 16 h + j (j < 16) and 64 + 16 h + j - 16 (h = l / 16);
+    K block b = k / 32 of row m is scaled by 2^(s - 127), s the scale of lane
+    m + 16 b; sums of small scaled integers are exact."""
+    api = _api()
+    rng = np.random.default_rng(23 if trial == "random" else 29)
+    A = rng.integers(-16, 17, size=(16, 128))
+    B = rng.integers(-16, 17, size=(128, 16))
+    if trial == "random":
+        S = rng.choice([127, 132], size=(16, 4))
+    else:
+        # the tile's use: block scales 32^f, the top digit f = 2 in {-1, 0, 1}
+        S = np.tile(np.array([127, 132, 137, 127]), (16, 1))
+        A[:, 64:96] = rng.integers(-1, 2, size=(16, 32))
+    a = np.zeros(64 * 32 + 64 * 4, np.uint8)
+    b = np.zeros((64, 32), np.uint8)
+    scales = np.zeros(64, np.int32)
+    for l in range(64):
+        h, r = l // 16, l % 16
+        scales[l] = S[r, h]
+        for j in range(32):
+            k = _k128_slot(h, j)
+            a[l * 32 + j] = e4m3(A[r, k])
+            b[l, j] = e4m3(B[k, r])
+    a[64 * 32:] = scales.view(np.uint8)
+    d = torch.zeros((64, 4), dtype=torch.float32, device=gpu)
+    api.mfma_probe(7, torch.from_numpy(a).to(gpu), torch.from_numpy(b).to(gpu), d)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    w = np.exp2(S.astype(np.int64) - 127).astype(np.int64)  # [row, block]
+    ref = np.zeros((16, 16), np.int64)
+    for blk in range(4):
+        ks = slice(32 * blk, 32 * blk + 32)
+        ref += (A[:, ks] * w[:, blk:blk + 1]) @ B[ks, :]
+    got = np.zeros((16, 16))
+    for l in range(64):
+        for v in range(4):
+            got[4 * (l // 16) + v, l % 16] = D[l, v]
+    assert np.array_equal(got, ref)
+
+
 def test_i8_mfma_16x16x64_layout_and_exactness(gpu):
     api = _api()
     rng = np.random.default_rng(12)
