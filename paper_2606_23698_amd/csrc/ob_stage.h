@@ -53,8 +53,8 @@ struct Shape {
 };
 
 // Data operand planes of one modulus: INT8 three Karatsuba forms (a~, b~,
-// a~ + b~), FP16 and FP8 the two forms (a~, b~) of the four-product complex
-// GEMM.
+// a~ + b~), FP16 the two forms (a~, b~) of the four-product complex GEMM,
+// FP8 room for three (the full-length tile adds -b~).
 __host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
   return (sub == SUB_FP16 ? 2 : 3) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
 }
@@ -100,41 +100,6 @@ __device__ __forceinline__ void put_digits_fp8(unsigned char* dig, int form, int
     float d0 = __builtin_fmaf(-32.0f, t1, v);
     uint32_t wd = fp8_pack2<false>(d0, t1, 0u);
     *(uint16_t*)(dig + fp8_slot<CHB, NT>(form, jc, 2 * s)) = (uint16_t)wd;
-  }
-}
-
-// Full-length FP8 tile: the digits of four consecutive indices s0 .. s0 + 3
-// (s0 % 4 == 0) of column jc in one form.  ND = 3: twelve slots 3 s0 ..
-// 3 s0 + 11, written as three aligned 32-bit words (a 4-byte-aligned word
-// never straddles a lane's 8 bytes or a 32-slot chunk); ND = 2: eight slots,
-// one lane's 8 bytes.
-template <int CHB, int NT, int ND>
-__device__ __forceinline__ void put_digits_fp8_x4(unsigned char* dig, int form, int jc, int s0, const float* v) {
-  float d[4][3];
-#pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const float t1 = __builtin_rintf(v[u] * 0.03125f);
-    d[u][0] = __builtin_fmaf(-32.0f, t1, v[u]);
-    if (ND == 3) {
-      const float t2 = __builtin_rintf(t1 * 0.03125f);
-      d[u][1] = __builtin_fmaf(-32.0f, t2, t1);
-      d[u][2] = t2;
-    } else {
-      d[u][1] = t1;
-    }
-  }
-  if (ND == 3) {
-    const uint32_t w0 = fp8_pack2<true>(d[0][2], d[1][0], fp8_pack2<false>(d[0][0], d[0][1], 0u));
-    const uint32_t w1 = fp8_pack2<true>(d[2][0], d[2][1], fp8_pack2<false>(d[1][1], d[1][2], 0u));
-    const uint32_t w2 = fp8_pack2<true>(d[3][1], d[3][2], fp8_pack2<false>(d[2][2], d[3][0], 0u));
-    const int b = 3 * s0;
-    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b)) = w0;
-    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b + 4)) = w1;
-    *(uint32_t*)(dig + fp8_slot<CHB, NT>(form, jc, b + 8)) = w2;
-  } else {
-    const uint32_t w0 = fp8_pack2<true>(d[1][0], d[1][1], fp8_pack2<false>(d[0][0], d[0][1], 0u));
-    const uint32_t w1 = fp8_pack2<true>(d[3][0], d[3][1], fp8_pack2<false>(d[2][0], d[2][1], 0u));
-    *(uint2*)(dig + fp8_slot<CHB, NT>(form, jc, 2 * s0)) = make_uint2(w0, w1);
   }
 }
 
@@ -398,7 +363,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   // the whole single-slot chunk, for all its columns), so it skips this.
   if (!(FULL && KMAX == 32))
     for (int x = tid * 16; x < 2 * DIG; x += kThreads * 16) *(uint4*)(smem + x) = make_uint4(0, 0, 0, 0);
-  // (the full-length FP8 tile: every modulus writes all 3 or 2 chunks it reads)
+  // (the full-length FP8 tile: every modulus writes every digit plane it reads)
   __syncthreads();
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
@@ -641,10 +606,11 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) ----
     float Dv[4], Ev[4], Fv[4];
     if (SUB == SUB_FP8) {
-      // four real products on the digit planes: R = Re A x~ - Im A y~,
-      // I = Im A x~ + Re A y~, one accumulator per matrix digit f (every
-      // partial sum is an integer of magnitude <= 2 * 32 * 3 * 16 * 16 <
-      // 2^24); R = sum_f 32^f accR[f], |R| < 2^22, exact in FP32
+      // four real products on the digit planes.  General tile: R = Re A x~ -
+      // Im A y~ and I = Im A x~ + Re A y~ on the K = 32 instruction, one
+      // accumulator per matrix digit f (every partial sum is an integer of
+      // magnitude <= 2 * 32 * 3 * 16 * 16 < 2^24); R = sum_f 32^f accR[f],
+      // |R| < 2^22, exact in FP32.
       const int ndp = nd;  // K slots per index (3 digits: 96 slots, three chunks, at K = 32)
       const int nch = (ndp * K + 31) >> 5;
       v4f accR[3], accI[3];
