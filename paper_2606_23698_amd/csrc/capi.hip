@@ -961,7 +961,7 @@ static obfft_status_t batch_plan_create(obfft_plan_t* out, int count, const int6
         first[pass * count + i] = acc;
         acc += tiles[pass * count + i];
         full &= bp->h_desc[pass * count + i].K == kclass_kmax(c) &&
-                (bp->substrate != SUB_FP8 || bp->h_desc[pass * count + i].fp8_full);
+                (bp->substrate != SUB_FP8 || (bp->h_desc[pass * count + i].fp8_full && bp->h_desc[pass * count + i].amat128));
       }
       bp->batch_full[pass][c] = full;
       bp->batch_total[pass][c] = acc;

@@ -919,7 +919,7 @@ static hipError_t launch_stage_k(const StageParams& P, dim3 grid, hipStream_t st
   }
   if (F && K == 32) return launch_stage_t<SUB, TGT, 32, F, H0, TAP>(P, grid, st);
   if constexpr (SUB == SUB_FP8)
-    if (K == 32 && P.fp8_full) return launch_stage_t<SUB, TGT, 32, true, H0, TAP>(P, grid, st);
+    if (K == 32 && P.fp8_full && P.amat128) return launch_stage_t<SUB, TGT, 32, true, H0, TAP>(P, grid, st);
   return launch_stage_t<SUB, TGT, 32, false, H0, TAP>(P, grid, st);
 }
 
