@@ -5,8 +5,9 @@
  * per axis (Sec. 2, "The Bailey six-step FFT": input index j = j1 + p j2,
  * output index k = k2 + q k1) whose two DFT stages are Ozaki-II residue GEMMs
  * on MFMA (Sec. 2, Eq. ozaki) with the twiddles fused into the second-stage
- * operands (Sec. 4.1, Eq. twiddle-fusion), complex products by the 3-real-GEMM
- * Karatsuba split combined in the residue domain (Alg. 1), and an exact CRT
+ * operands (Sec. 4.1, Eq. twiddle-fusion), complex products as four real
+ * GEMMs accumulated into R and I (the paper's Karatsuba split, Alg. 1, trades
+ * one product for combines that cost more on this part), and an exact CRT
  * reconstruction: a Phase-A GEMM on FP16 MFMA over canonical residues
  * (Sec. 4.2, Eqs. fcrt, slicing, phaseAcost) followed by a Kulisch fixed-point
  * accumulation, a two-sided modulo-M lift and one correctly rounded pack
@@ -71,10 +72,12 @@ enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
 
 /* MFMA substrate of the residue GEMMs.  All substrates produce bit-identical
  * outputs (the residues of an exact integer product are unique).
- *   FP8  : E4M3 radix-32 digit planes, v_mfma_f32_16x16x32_fp8_fp8, FP32
- *          accumulation, three Karatsuba products
+ *   FP8  : E4M3 radix-32 digit planes, FP32 accumulation, four real
+ *          products; at K = 32 the scaled v_mfma_scale_f32_16x16x128_f8f6f4
+ *          with the matrix-digit weights in its block scales, otherwise
+ *          v_mfma_f32_16x16x32_fp8_fp8 with one accumulator per digit
  *   INT8 : 8-bit limbs (radix 128), v_mfma_i32_16x16x64_i8, INT32
- *          accumulation, three Karatsuba products
+ *          accumulation, four real products
  *   FP16 : whole FP16 matrix residues against radix-128 data limbs (the
  *          first 4 moduli of an FP64 set, 3 of an FP32 set) or against one
  *          FP16 residue per index (the later moduli, each of which must

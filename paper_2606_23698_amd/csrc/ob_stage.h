@@ -4,9 +4,11 @@
 // One launch computes one Bailey stage of one axis for every line of the
 // array (Alg. 1): per contraction column it extracts the shared power-of-two
 // scale, quantises Re and Im to k-bit integers, reduces them modulo every
-// m_i (Sec. 2, Eq. ozaki), runs the three Karatsuba real GEMMs per modulus on
-// MFMA (Sec. 2; Sec. 4.1 Eq. wmma), combines R = D - E and I = F - D - E in
-// the residue domain and canonicalises them (Alg. 1), and reconstructs each
+// m_i (Sec. 2, Eq. ozaki), runs the complex residue GEMM per modulus on MFMA
+// as four real products accumulated straight into R and I (Sec. 2; Sec. 4.1
+// Eq. wmma; the paper's three Karatsuba products plus combines cost vector
+// work that the matrix cores do not), reduces R and I to centred residues
+// in the residue domain (Alg. 1), and reconstructs each
 // output exactly by the Phase-A FP16 MFMA GEMM (Sec. 4.2) and the Kulisch
 // Phase B with the two-sided lift and a correctly rounded pack (Sec. 5.1,
 // Alg. 2).  The only FP64 arithmetic is the exponent/scale extraction and
@@ -52,11 +54,11 @@ struct Shape {
   static constexpr int KQ = (KMAX + TPC - 1) / TPC;     // elements per thread
 };
 
-// Data operand planes of one modulus: INT8 three Karatsuba forms (a~, b~,
-// a~ + b~), FP16 the two forms (a~, b~) of the four-product complex GEMM,
-// FP8 room for three (the full-length tile adds -b~).
+// Data operand planes of one modulus: the two forms (a~, b~) of the
+// four-product complex GEMM, FP8 room for three (the full-length tile adds
+// -b~).
 __host__ __device__ constexpr int dig_bytes(int sub, int kmax, int nt) {
-  return (sub == SUB_FP16 ? 2 : 3) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
+  return (sub == SUB_FP8 ? 3 : 2) * chunks_for(sub, kmax) * nt * 64 * (sub == SUB_FP8 ? 8 : 16);
 }
 
 // LDS of one workgroup: two digit buffers (even / odd moduli), the column
@@ -70,7 +72,7 @@ struct StageLds {
 };
 
 // Writes the digit planes of residue v (exact small integer) of column jc,
-// contraction index s, Karatsuba form `form` (0: a~, 1: b~, 2: a~ + b~).
+// contraction index s, data form `form` (0: a~, 1: b~).
 // Byte offset of K-slot `slot` of column jc in one form's FP8 planes
 // ([chunk][N-tile][lane][8 bytes]: slot kk of a chunk sits in lane
 // (jc % 16) + 16 (kk / 8) at byte kk % 8).
@@ -144,7 +146,7 @@ __device__ __forceinline__ int i8_slot(int jc, int s) {
 }
 
 // Writes the limb pairs of KQ consecutive contraction indices s0.. of one
-// column and one Karatsuba form (KQ = 1, 2, 4 stay inside one lane's 16
+// column and one data form (KQ = 1, 2, 4 stay inside one lane's 16
 // bytes and take one store; KQ = 3 may cross a lane and stores per index).
 template <int KQ>
 __device__ __forceinline__ void put_limbs(unsigned char* form_base, int jc, int s0, const uint32_t* w) {
@@ -504,7 +506,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     const int nd = (SUB == SUB_FP8) ? (FULL ? (i < kFp16Split[TGT] ? 3 : 2) : MC.nd[i]) : 2;
     const uint8_t* amod = amat + i * P.amat_mod_stride;
     // A-operand planes of this modulus, issued before the deconstruction so
-    // that their latency overlaps it (INT8: 3 forms x 2 limbs, one chunk).
+    // that their latency overlaps it (INT8: Re A, Im A, -Im A x 2 limbs, one chunk).
     v4i ai8[3][2];
     if (SUB == SUB_INT8 && mt_active) {
 #pragma unroll
@@ -533,7 +535,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     // ---- deconstruction: residues and digit planes (Sec. 2, Eq. ozaki) ----
     // indices past K (when KQ does not divide K) store zero limbs: the FP16
     // planes must not see stray NaN patterns even against zero matrix slots
-    uint32_t la[KQ] = {}, lb[KQ] = {}, ls[KQ] = {};
+    uint32_t la[KQ] = {}, lb[KQ] = {};
     float ra16[KQ] = {}, rb16[KQ] = {};
 #pragma unroll
     for (int u = 0; u < KQ; u++) {
@@ -556,7 +558,6 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
           int rb = (int)__builtin_fma(-md, __builtin_rint(br[u] * imd), br[u]);
           la[u] = i8_limbs(ra);
           lb[u] = i8_limbs(rb);
-          ls[u] = i8_limbs(ra + rb);
         } else if (!FULL) {
           // FP8: digit planes of a~ and b~ (four real products, as FP16)
           ra16[u] = TGT == 1 ? reduce_f32(arf[u], mf, imf) : residue_f64(ar[u], md, imd);
@@ -569,7 +570,6 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     if (SUB == SUB_INT8 && s0 < K) {
       put_limbs<KQ>(dig, jc, s0, la);
       put_limbs<KQ>(dig + kI8FormBytes, jc, s0, lb);
-      put_limbs<KQ>(dig + 2 * kI8FormBytes, jc, s0, ls);
     }
     if (SUB == SUB_FP8 && FULL) {
       // one form at a time: its four residues, then their digits
@@ -603,7 +603,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     if (i > 0 && mt_active) combine(i - 1, pD, pE, pF, pmf, pimf);
     __syncthreads();
     if (!mt_active) continue;
-    // ---- residue GEMMs D, E, F (Karatsuba, Sec. 2) ----
+    // ---- residue GEMMs: R and I of the complex product (Sec. 2) ----
     float Dv[4], Ev[4], Fv[4];
     if (SUB == SUB_FP8) {
       // four real products on the digit planes.  General tile: R = Re A x~ -
@@ -716,21 +716,22 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
         Fv[v] = accI[v];
       }
     } else {
-      v4i acc[3][2];
+      // four real products per matrix limb f in INT32: R = Re A x~ + (-Im A) y~,
+      // I = Im A x~ + Re A y~; R = accR[0] + 128 accR[1] is an integer of
+      // magnitude <= 2 * 32 * 1019 * (127 + 16) < 2^24, exact in FP32
+      const v4i bx = *(const v4i*)(dig + (nt * 64 + lane) * 16);
+      const v4i by = *(const v4i*)(dig + kI8FormBytes + (nt * 64 + lane) * 16);
+      v4i accR[2], accI[2];
 #pragma unroll
-      for (int form = 0; form < 3; form++) {
-        v4i bop = *(const v4i*)(dig + ((form * NT + nt) * 64 + lane) * 16);
-#pragma unroll
-        for (int f = 0; f < 2; f++) acc[form][f] = mfma_i8(ai8[form][f], bop, (v4i){0, 0, 0, 0});
+      for (int f = 0; f < 2; f++) {
+        accR[f] = mfma_i8(ai8[2][f], by, mfma_i8(ai8[0][f], bx, (v4i){0, 0, 0, 0}));
+        accI[f] = mfma_i8(ai8[0][f], by, mfma_i8(ai8[1][f], bx, (v4i){0, 0, 0, 0}));
       }
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        int d = acc[0][0][v] + (acc[0][1][v] << 7);
-        int e = acc[1][0][v] + (acc[1][1][v] << 7);
-        int f = acc[2][0][v] + (acc[2][1][v] << 7);
-        Dv[v] = (float)(d - e);          // R (combined in INT32, exact)
+        Dv[v] = (float)(accR[0][v] + (accR[1][v] << 7));
         Ev[v] = 0.0f;
-        Fv[v] = (float)(f - d - e);      // I
+        Fv[v] = (float)(accI[0][v] + (accI[1][v] << 7));
       }
     }
     // the combine of this modulus runs after the next one's deconstruction,

@@ -488,9 +488,8 @@ void build_operand_planes(const ModSet& H, const std::vector<int64_t>& roots, in
           matrix_entry(roots, N, p, q, stage, g, t, s, direction, &c, &sn);
           cval[(0 * K + t) * K + s] = centred(c, m);
           cval[(1 * K + t) * K + s] = centred(sn, m);
-          // Karatsuba (INT8): Re A, Im A, Re A + Im A; FP16 and FP8 (four
-          // real products): Re A, Im A, -Im A
-          cval[(2 * K + t) * K + s] = substrate == SUB_INT8 ? centred(c + sn, m) : centred(-sn, m);
+          // four real products on every substrate: Re A, Im A, -Im A
+          cval[(2 * K + t) * K + s] = centred(-sn, m);
         }
       if (substrate == SUB_FP16) {
         // [form][M-tile][chunk][lane][8 halves]; slot 32 ch + 8 (lane / 16) + j
