@@ -155,6 +155,22 @@ def test_persistent_claim_sizes(gpu):
                 assert torch.equal(o, r), (c, rep, i, shapes[i])
 
 
+def test_fp8_batch_class_with_mixed_lengths(gpu):
+    """FP8 batch whose K = 32 stage shares a launch with a K = 24 stage (768 =
+    24 x 32): the class runs the general tile, which reads the general plane
+    layout of the K = 32 member (its plan also holds the full-length tile's);
+    outputs equal the single FP8 plans, which take the full-length tile."""
+    from paper_2606_23698_amd import api
+    shapes = [(2, 2, 1024), (2, 2, 768)]
+    xs = [torch.from_numpy(inputs.uniform(s, 90 + i)).to(gpu) for i, s in enumerate(shapes)]
+    ref = [api.Plan(s, substrate="fp8").forward(x) for s, x in zip(shapes, xs)]
+    bp = api.BatchPlan(shapes, substrate="fp8")
+    outs = bp.forward(xs)
+    torch.cuda.synchronize()
+    for o, r, s in zip(outs, ref, shapes):
+        assert torch.equal(o, r), s
+
+
 def test_fp8_batch_with_full_length_members(gpu):
     """FP8 batches (one launch per pass and class): a class of K = 32 stages
     takes the full-length FP8 tile; outputs equal the single FP8 plans."""
