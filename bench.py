@@ -160,6 +160,14 @@ def batch_throughput(api, inputs, steps):
     ysp = [torch.empty_like(x) for x in xs]
     ms_p, _ = time_steps(lambda: bp.forward(xs, ysp), steps, 1)
     claim = bp.claim()
+    # the claim size of the persistent launch: fewer releases (each an L2
+    # write-back) against a coarser dependency grain
+    sweep = {}
+    for c in (32, 128, 256):
+        bp.set_claim(c)
+        sweep[c] = round(time_steps(lambda: bp.forward(xs, ysp), steps, 1)[0], 3)
+    sweep[claim] = round(ms_p, 3)
+    bp.set_claim(claim)
     plans = [api.get_plan(s) for s in shapes]
     ys2 = [torch.empty_like(x) for x in xs]
 
@@ -193,6 +201,7 @@ def batch_throughput(api, inputs, steps):
     return {"transforms": len(shapes), "elements": elems, "ms": round(ms_b, 3), "loop_ms": round(ms_l, 3),
             "speedup_vs_loop": round(ms_l / ms_b, 3), "bit_identical_to_loop": same,
             "persistent_ms": round(ms_p, 3), "persistent_claim": claim,
+            "persistent_ms_by_claim": {str(k): sweep[k] for k in sorted(sweep)},
             "persistent_bit_identical_to_loop": same_p,
             "tuned": {"ms": round(ms_t, 3), "loop_ms": round(ms_tl, 3), "speedup_vs_loop": round(ms_tl / ms_t, 3),
                       "bit_identical_to_tuned_loop": same_t, "tune_s": round(tune_s, 1),
