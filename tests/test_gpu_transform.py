@@ -60,7 +60,7 @@ def test_forward_32cubed_bit_exact(gpu, substrate):
     ((18, 4, 2), ((3, 6), (1, 4), (2, 1))),   # forced odd / unit factors
     ((96, 4, 48), ((8, 12), (2, 2), (4, 12))),  # full-length K = 12 and K = 8 launches
 ])
-@pytest.mark.parametrize("substrate", ["fp8", "fp16"])
+@pytest.mark.parametrize("substrate", ["fp8", "int8", "fp16"])
 def test_forward_small_shapes_bit_exact(gpu, shape, pq, substrate):
     api = _api()
     x = inputs.uniform(shape, 7)
