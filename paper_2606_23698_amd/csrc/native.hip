@@ -22,6 +22,11 @@ constexpr int kNatThreads = 256;
 constexpr int kNatLdsComplex = 8192;   // 128 KiB of complex data per workgroup
 constexpr int kMaxPasses = 12;
 constexpr int kNatRegs = 32;           // complex values a thread holds during a pass
+// Arrays from this size on are streamed with nontemporal loads and stores by
+// the 4-step kernels.  Measured on gfx950: every axis of the 4, 8 and 16 GiB
+// shapes gets faster (1024^3: 21.7 -> 19.3 ms), while at 2 GiB (512^3) and
+// below the default cache policy is faster.
+constexpr int64_t kNatStreamBytes = int64_t(4) << 30;
 
 struct NatAxis {
   int64_t N, inner, outer;
@@ -248,10 +253,29 @@ struct RegDft {
   }
 };
 
+// Global loads and stores of the 4-step kernel; SM marks them nontemporal
+// (streaming: the lines are read once and written once).
+typedef double nat_d2 __attribute__((ext_vector_type(2)));
+template <bool SM>
+__device__ __forceinline__ double2 nat_load(const double2* p) {
+  if constexpr (SM) {
+    const nat_d2 t = __builtin_nontemporal_load((const nat_d2*)p);
+    return make_double2(t.x, t.y);
+  } else {
+    return *p;
+  }
+}
+template <bool SM>
+__device__ __forceinline__ void nat_store(double2* p, double2 v) {
+  if constexpr (SM) __builtin_nontemporal_store((nat_d2){v.x, v.y}, (nat_d2*)p);
+  else *p = v;
+}
+
 // NT threads per workgroup: 256, or 512 on a strided axis with R2 = 32, so
 // that a workgroup holds 16 lines and every global access of a wave covers
-// 16 neighbouring lines (256-byte runs instead of 128).
-template <int R1, int R2, bool STRIDED, int DIR, int NT = kNatThreads>
+// 16 neighbouring lines (256-byte runs instead of 128).  SM: nontemporal
+// global accesses, taken for arrays of at least kNatStreamBytes.
+template <int R1, int R2, bool STRIDED, int DIR, int NT = kNatThreads, bool SM = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void native_4step_kernel(const double2* in, double2* out, int64_t inner,
                                                                    int64_t nlines, const double2* tw,
                                                                    double post_scale) {
@@ -277,7 +301,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void na
   double2 v[R1];
 #pragma unroll
   for (int n1 = 0; n1 < R1; n1++)
-    v[n1] = valid1 ? src[(int64_t)(n1 * R2 + n2) * inner] : make_double2(0.0, 0.0);
+    v[n1] = valid1 ? nat_load<SM>(&src[(int64_t)(n1 * R2 + n2) * inner]) : make_double2(0.0, 0.0);
   RegDft<R1, DIR>::run(v, tw, N / R1);
   // X1[k1] sits at v[pos(k1)]; twiddle w_N^{n2 k1}
 #pragma unroll
@@ -328,56 +352,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void na
   for (int k2 = 0; k2 < R2; k2++) {
     double2 x = u[RegDft<R2, DIR>::pos(k2)];
     if (post_scale != 1.0) x = make_double2(x.x * post_scale, x.y * post_scale);
-    dst[(int64_t)(k1t + R1 * k2) * inner] = x;
+    nat_store<SM>(&dst[(int64_t)(k1t + R1 * k2) * inner], x);
   }
 }
 
+template <int R1, int R2, bool STRIDED, int NT, bool SM>
+static void launch_4step_k(const double2* in, double2* out, const NatAxis& A, int inverse, double ps, hipStream_t st) {
+  const int64_t nlines = A.outer * A.inner;
+  const int64_t grid = (nlines + NT / R2 - 1) / (NT / R2);
+  if (inverse)
+    hipLaunchKernelGGL((native_4step_kernel<R1, R2, STRIDED, -1, NT, SM>), dim3((unsigned)grid), dim3(NT), 0, st, in,
+                       out, A.inner, nlines, A.tw, ps);
+  else
+    hipLaunchKernelGGL((native_4step_kernel<R1, R2, STRIDED, 1, NT, SM>), dim3((unsigned)grid), dim3(NT), 0, st, in,
+                       out, A.inner, nlines, A.tw, ps);
+}
+
 template <int R1, int R2>
-static hipError_t launch_4step(const double2* in, double2* out, const NatAxis& A, int inverse, double ps,
+static hipError_t launch_4step(const double2* in, double2* out, const NatAxis& A, int inverse, double ps, bool stream,
                                hipStream_t st) {
-  constexpr int LPW = kNatThreads / R2;
   constexpr int NTS = R2 == 32 ? 2 * kNatThreads : kNatThreads;  // strided axes
-  constexpr int LPWS = NTS / R2;
-  int64_t nlines = A.outer * A.inner;
-  int64_t grid = (nlines + LPW - 1) / LPW;
-  bool strided = A.inner > 1;
-  if (strided) {
-    grid = (nlines + LPWS - 1) / LPWS;
-    if (inverse)
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, -1, NTS>), dim3((unsigned)grid), dim3(NTS), 0, st,
-                         in, out, A.inner, nlines, A.tw, ps);
-    else
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, true, 1, NTS>), dim3((unsigned)grid), dim3(NTS), 0, st,
-                         in, out, A.inner, nlines, A.tw, ps);
+  if (A.inner > 1) {
+    if (stream) launch_4step_k<R1, R2, true, NTS, true>(in, out, A, inverse, ps, st);
+    else launch_4step_k<R1, R2, true, NTS, false>(in, out, A, inverse, ps, st);
   } else {
-    if (inverse)
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, false, -1>), dim3((unsigned)grid), dim3(kNatThreads), 0,
-                         st, in, out, A.inner, nlines, A.tw, ps);
-    else
-      hipLaunchKernelGGL((native_4step_kernel<R1, R2, false, 1>), dim3((unsigned)grid), dim3(kNatThreads), 0,
-                         st, in, out, A.inner, nlines, A.tw, ps);
+    if (stream) launch_4step_k<R1, R2, false, kNatThreads, true>(in, out, A, inverse, ps, st);
+    else launch_4step_k<R1, R2, false, kNatThreads, false>(in, out, A, inverse, ps, st);
   }
   return hipGetLastError();
 }
 
 // Returns hipErrorNotSupported when N has no register split.
 static hipError_t launch_native_axis(const double2* in, double2* out, const NatAxis& A, int inverse, double ps,
-                                     hipStream_t st) {
+                                     bool stream, hipStream_t st) {
   switch (A.N) {
-    case 1024: return launch_4step<32, 32>(in, out, A, inverse, ps, st);
-    case 512: return launch_4step<16, 32>(in, out, A, inverse, ps, st);
-    case 256: return launch_4step<16, 16>(in, out, A, inverse, ps, st);
-    case 192: return launch_4step<12, 16>(in, out, A, inverse, ps, st);
-    case 128: return launch_4step<8, 16>(in, out, A, inverse, ps, st);
-    case 96: return launch_4step<6, 16>(in, out, A, inverse, ps, st);
-    case 64: return launch_4step<8, 8>(in, out, A, inverse, ps, st);
-    case 48: return launch_4step<6, 8>(in, out, A, inverse, ps, st);
-    case 32: return launch_4step<4, 8>(in, out, A, inverse, ps, st);
-    case 24: return launch_4step<3, 8>(in, out, A, inverse, ps, st);
-    case 16: return launch_4step<4, 4>(in, out, A, inverse, ps, st);
-    case 12: return launch_4step<3, 4>(in, out, A, inverse, ps, st);
-    case 8: return launch_4step<2, 4>(in, out, A, inverse, ps, st);
-    case 4: return launch_4step<2, 2>(in, out, A, inverse, ps, st);
+    case 1024: return launch_4step<32, 32>(in, out, A, inverse, ps, stream, st);
+    case 512: return launch_4step<16, 32>(in, out, A, inverse, ps, stream, st);
+    case 256: return launch_4step<16, 16>(in, out, A, inverse, ps, stream, st);
+    case 192: return launch_4step<12, 16>(in, out, A, inverse, ps, stream, st);
+    case 128: return launch_4step<8, 16>(in, out, A, inverse, ps, stream, st);
+    case 96: return launch_4step<6, 16>(in, out, A, inverse, ps, stream, st);
+    case 64: return launch_4step<8, 8>(in, out, A, inverse, ps, stream, st);
+    case 48: return launch_4step<6, 8>(in, out, A, inverse, ps, stream, st);
+    case 32: return launch_4step<4, 8>(in, out, A, inverse, ps, stream, st);
+    case 24: return launch_4step<3, 8>(in, out, A, inverse, ps, stream, st);
+    case 16: return launch_4step<4, 4>(in, out, A, inverse, ps, stream, st);
+    case 12: return launch_4step<3, 4>(in, out, A, inverse, ps, stream, st);
+    case 8: return launch_4step<2, 4>(in, out, A, inverse, ps, stream, st);
+    case 4: return launch_4step<2, 2>(in, out, A, inverse, ps, stream, st);
     default: return hipErrorNotSupported;
   }
 }
@@ -479,6 +501,7 @@ hipError_t native_execute(NativePlan* np, const void* in, void* out, void* /*ws*
     attr = true;
   }
   int64_t total = np->n[0] * np->n[1] * np->n[2];
+  const bool stream = total * (int64_t)sizeof(double2) >= kNatStreamBytes;
   const double2* src = (const double2*)in;
   for (int k = 0; k < 3; k++) {
     int a = 2 - k;
@@ -496,7 +519,7 @@ hipError_t native_execute(NativePlan* np, const void* in, void* out, void* /*ws*
       src = (const double2*)out;
       continue;
     }
-    hipError_t e = launch_native_axis(src, (double2*)out, A, inverse, ps, st);
+    hipError_t e = launch_native_axis(src, (double2*)out, A, inverse, ps, stream, st);
     if (e == hipErrorNotSupported) {
       (void)hipGetLastError();
       int64_t nlines = A.outer * A.inner;
