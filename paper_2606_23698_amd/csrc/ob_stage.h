@@ -336,6 +336,16 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile addressing stays scalar
   const int64_t cstart = ctile * NCR;
+  // Wave priority: a wave runs at priority 1 from here (column tables, input
+  // loads, exponents) to the barrier after the exponents, and in every modulus
+  // from the top of the iteration to its barrier (A-plane loads,
+  // deconstruction, digit stores, the deferred combine); at priority 0 in the
+  // GEMMs and the epilogue.  The issue arbiter then serves the waves of
+  // workgroups that are starting, and of those that hold their next barrier,
+  // first, while the waves past it fill the gaps: about 3 % off the 1024^3
+  // transform, measured on several machines.  The start of the tile carries
+  // most of it; priority in the epilogue instead costs 0.5-1.5 %.
+  __builtin_amdgcn_s_setprio(1);
   if (tid < NCR) {
     // column c = (i, g, o) of the stage, i fastest (stage 2: g is the tile's)
     const int64_t c = cstart + tid;
@@ -369,15 +379,6 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
   __syncthreads();
 
   // ---- load, column exponent, quantisation (Alg. 1 scaling invariant) ----
-  // Wave priority: a wave runs at priority 1 from here to the barrier that
-  // ends this phase, and in every modulus from the top of the iteration to
-  // its barrier (A-plane loads, deconstruction, digit stores, the deferred
-  // combine); at priority 0 in the GEMMs and the epilogue.  The issue
-  // arbiter then serves the waves that hold their workgroup's next barrier
-  // first, while the waves past it fill the gaps: about 3 % off the 1024^3
-  // transform (priority 1 for the input loads alone: 2.2-2.6 %; high
-  // priority in the epilogue instead cost 0.6 %).
-  __builtin_amdgcn_s_setprio(1);
   const int jc = tid % NCOL, part = tid / NCOL;
   const int blk = PK ? part / (TPC / NP) : 0;  // packed: which column of the group
   const int rc = NP * jc + blk;                // this thread's column in the tables
