@@ -65,9 +65,16 @@ typedef enum {
                                      workspace exceeds the library's fixed scratch array */
 } obfft_status_t;
 
-/* Precision target.  FP64: r = 12 moduli (Sec. 2 shipping set), k = 53.
- * FP32: r = 6 moduli {2039, 2029, 2027, 1024, 961, 841}, log2 M = 62.6, k = 24,
- * S = 8 (Sec. 7, "Ozaki-II for FP32"). */
+/* Precision target.  FP64: r = 12 moduli, k = 53; FP32: r = 6 moduli,
+ * k = 24, S = 8 (Sec. 7, "Ozaki-II for FP32").  The transform plans default
+ * to pairwise coprime sets with every modulus at most 1024 (FP64: 1024, 1023,
+ * 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967, log2 M = 119.6;
+ * FP32: 1024, 1023, 1021, 1019, 1013, 1009, log2 M = 60.0), which the FP16
+ * residue GEMM takes whole.  The paper's sets (Sec. 2: 2039, 2029, 2027, 1089,
+ * 1024, 961, 841, 625, 529, 511, 491, 487, log2 M = 117.9; Sec. 7: 2039, 2029,
+ * 2027, 1024, 961, 841, log2 M = 62.6) serve the standalone CRT entry points
+ * and the H0 reduction, and any plan through moduli_override.  Transform
+ * outputs do not depend on the set: the stage results are exact integers. */
 enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
 
 /* MFMA substrate of the residue GEMMs.  All substrates produce bit-identical
@@ -78,13 +85,13 @@ enum { OBFFT_PREC_FP64 = 0, OBFFT_PREC_FP32 = 1 };
  *          v_mfma_f32_16x16x32_fp8_fp8 with one accumulator per digit
  *   INT8 : 8-bit limbs (radix 128), v_mfma_i32_16x16x64_i8, INT32
  *          accumulation, four real products
- *   FP16 : whole FP16 matrix residues against radix-128 data limbs (the
- *          first 4 moduli of an FP64 set, 3 of an FP32 set) or against one
- *          FP16 residue per index (the later moduli, each of which must
- *          satisfy 64 h (h + e) <= 2^24, h = floor(m/2), e = 0 for a power
- *          of two and 2 otherwise, else OBFFT_UNSUPPORTED_SIZE),
- *          v_mfma_f32_16x16x32_f16, exact FP32
- *          accumulation of the four real products straight into Re and Im
+ *   FP16 : whole FP16 matrix residues against one FP16 data residue per
+ *          index (every modulus must satisfy 64 h (h + e) <= 2^24, h =
+ *          floor(m/2), e = 0 for a power of two and 2 otherwise, i.e.
+ *          m <= 1024, else OBFFT_UNSUPPORTED_SIZE); with the H0 reduction
+ *          the first 4 moduli of its set enter as radix-128 data limbs
+ *          instead.  v_mfma_f32_16x16x32_f16, exact FP32 accumulation of
+ *          the four real products straight into Re and Im
  *   AUTO : FP16 when the modulus set allows it (both default sets do), else
  *          INT8 */
 enum { OBFFT_SUB_FP8 = 0, OBFFT_SUB_INT8 = 1, OBFFT_SUB_FP16 = 2, OBFFT_SUB_AUTO = 3 };
@@ -107,7 +114,8 @@ typedef struct {
   int substrate;            /* OBFFT_SUB_* */
   int p[3];                 /* per axis (n1, n2, n3); 0 = library default */
   int q[3];                 /* per axis; p*q must equal the extent */
-  int n_moduli_override;    /* 0 = the precision's set; else use moduli_override */
+  int n_moduli_override;    /* 0 = the default set of the precision (and reduction);
+                               else use moduli_override */
   const int32_t* moduli_override; /* host pointer, pairwise coprime, each < 2048 */
   int reduction;            /* OBFFT_RED_* (0 = default) */
   int group_block;          /* tile order of stage 2 on the contiguous axis: the number of

@@ -42,8 +42,18 @@ hipError_t native_execute(NativePlan* np, const void* in, void* out, void* ws, i
 
 using namespace obfft;
 
+// The paper's modulus sets (Sec. 2): the standalone CRT entry points and the
+// fold-and-add reduction use them.
 static const int32_t kModFP64[12] = {2039, 2029, 2027, 1089, 1024, 961, 841, 625, 529, 511, 491, 487};
 static const int32_t kModFP32[6] = {2039, 2029, 2027, 1024, 961, 841};
+// Default sets of the transform plans: pairwise coprime, every modulus at
+// most 1024, so each residue is one FP16 slot of the residue GEMM (no limb
+// split of the data).  log2 M = 119.58 (FP64 target, above the 114 bits that
+// K = 32 needs) and 59.95 (FP32 target, above 56); the epilogue shape is the
+// same as with the paper's sets (15 / 8 byte slices of u_k, 6 of w_k).  The
+// stage results are exact integers, so the outputs do not depend on the set.
+static const int32_t kModStageFP64[12] = {1024, 1023, 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967};
+static const int32_t kModStageFP32[6] = {1024, 1023, 1021, 1019, 1013, 1009};
 
 struct DevPlanes {
   OperandPlanes L;
@@ -176,7 +186,8 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   int sub = opt->substrate;
   plan->substrate = sub;
   plan->kbits = plan->precision == OBFFT_PREC_FP32 ? 24 : 53;
-  const int32_t* mods = plan->precision == OBFFT_PREC_FP32 ? kModFP32 : kModFP64;
+  const bool h0 = opt->reduction == OBFFT_RED_H0;
+  const int32_t* mods = plan->precision == OBFFT_PREC_FP32 ? kModStageFP32 : (h0 ? kModFP64 : kModStageFP64);
   int r = plan->precision == OBFFT_PREC_FP32 ? 6 : 12;
   if (opt->n_moduli_override) {
     if (!opt->moduli_override) return OBFFT_INVALID_VALUE;
@@ -187,7 +198,7 @@ static obfft_status_t plan_build(obfft_plan_t plan, const obfft_options_t* opt) 
   if (!build_modset(mods, r, plan->H, err)) return OBFFT_INVALID_VALUE;
   // FP16 needs every modulus past the split to fit one slot per index; AUTO
   // takes FP16 when the set allows it, else INT8
-  const int fp16_split = kFp16Split[plan->precision == OBFFT_PREC_FP32 ? 1 : 0];
+  const int fp16_split = obfft::fp16_split(plan->precision == OBFFT_PREC_FP32 ? 1 : 0, h0);
   bool fp16_ok = true;
   for (int i = fp16_split; i < plan->H.r; i++) fp16_ok = fp16_ok && fp16_single_slot_ok(plan->H.m[i]);
   if (sub == OBFFT_SUB_AUTO) sub = fp16_ok ? OBFFT_SUB_FP16 : OBFFT_SUB_INT8;

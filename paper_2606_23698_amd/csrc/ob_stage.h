@@ -515,7 +515,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     // FP8 digits per residue: 3 for the moduli before the split (> 1052),
     // else 2; the full-length tile takes them from the position (the plan
     // checks that its modulus set follows this rule)
-    const int nd = (SUB == SUB_FP8) ? (FULL ? (i < kFp16Split[TGT] ? 3 : 2) : MC.nd[i]) : 2;
+    const int nd = (SUB == SUB_FP8) ? (FULL ? (i < fp16_split(TGT, H0) ? 3 : 2) : MC.nd[i]) : 2;
     const uint8_t* amod = amat + i * P.amat_mod_stride;
     // A-operand planes of this modulus, issued before the deconstruction so
     // that their latency overlaps it (INT8: Re A, Im A, -Im A x 2 limbs, one chunk).
@@ -530,7 +530,7 @@ __device__ __forceinline__ void stage_tile(const PT& P, int64_t ctile, int64_t g
     }
     // FP16: planes of Re A, Im A and -Im A, CH16 chunks of 32 slots each
     // (moduli past the split use chunk 0 only: one slot per index)
-    const bool split16 = i < kFp16Split[TGT];
+    const bool split16 = i < fp16_split(TGT, H0);
     const int nch = split16 ? nch16 : 1;
     v8h a16[3][CH16];
     if (SUB == SUB_FP16 && mt_active) {

@@ -23,14 +23,19 @@ __host__ __device__ constexpr int fp16_pack(int sub, int K) {
   return sub != SUB_FP16 ? 1 : K <= 4 ? 4 : K <= 8 ? 2 : 1;
 }
 
-// FP16 substrate: the first kFp16Split[precision] moduli of a set enter the
+// FP16 substrate: the first fp16_split(...) moduli of a set enter the
 // residue GEMM as two radix-128 limbs per index; every later modulus as one
 // FP16 slot per index, which needs 2 kMaxK h (h + e) <= 2^24 with h =
 // floor(m/2), e = 0 for a power of two (its residues are exact, |r| <= h)
 // and 2 otherwise: the largest possible partial sum of a 32-term,
-// two-product accumulation, kept exact in FP32.  The default sets satisfy it
-// from index 4 (r = 12: 1024, 961, 841, ...) and 3 (r = 6: 1024, 961, 841).
+// two-product accumulation, kept exact in FP32 (every m <= 1024 passes).
+// The paper's sets satisfy it from index 4 (r = 12: 1024, 961, 841, ...)
+// and 3 (r = 6: 1024, 961, 841); the fold-and-add reduction, which needs the
+// paper's reduction-friendly moduli, keeps that split.  The default stage
+// sets have every modulus at most 1024, so the reciprocal-reduction kernels
+// take every modulus as one slot (no limb split).
 constexpr int kFp16Split[2] = {4, 3};
+__host__ __device__ constexpr int fp16_split(int tgt, bool h0) { return h0 ? kFp16Split[tgt] : 0; }
 
 // Everything the CRT epilogue needs: Sec. 4.2 (Phase A, byte slices of
 // u_k) and Sec. 5.1 (fractional lift, bias, M).

@@ -13,13 +13,19 @@ using namespace obfft;
 
 static const int32_t kFP64[12] = {2039, 2029, 2027, 1089, 1024, 961, 841, 625, 529, 511, 491, 487};
 static const int32_t kFP32[6] = {2039, 2029, 2027, 1024, 961, 841};
+// the default sets of the transform plans (every modulus at most 1024, no limb split)
+static const int32_t kStageFP64[12] = {1024, 1023, 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967};
+static const int32_t kStageFP32[6] = {1024, 1023, 1021, 1019, 1013, 1009};
 
 int main() {
   uint64_t sum = 0;
-  for (int prec = 0; prec < 2; prec++) {
+  for (int cfg = 0; cfg < 4; cfg++) {
+    const int prec = cfg & 1, stage_set = cfg >> 1;
+    const int split = stage_set ? 0 : (prec ? 3 : 4);
     ModSet H;
     std::string err;
-    if (!build_modset(prec ? kFP32 : kFP64, prec ? 6 : 12, H, err)) {
+    const int32_t* mods = stage_set ? (prec ? kStageFP32 : kStageFP64) : (prec ? kFP32 : kFP64);
+    if (!build_modset(mods, prec ? 6 : 12, H, err)) {
       std::printf("build_modset: %s\n", err.c_str());
       return 1;
     }
@@ -45,10 +51,10 @@ int main() {
           for (int dir = 0; dir < 2; dir++) {
             std::vector<uint8_t> bytes;
             OperandPlanes L;
-            build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, prec ? 3 : 4, bytes, L);
+            build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, split, bytes, L);
             for (uint8_t b : bytes) sum = sum * 31 + b;
             // the full-length FP8 tile's layout (K = 32 stages)
-            build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, prec ? 3 : 4, bytes, L, 1);
+            build_operand_planes(H, roots, s[0], s[1], s[2], stage, dir, sub, split, bytes, L, 1);
             for (uint8_t b : bytes) sum = sum * 31 + b;
           }
     }

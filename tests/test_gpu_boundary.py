@@ -94,7 +94,7 @@ def test_debug_tap_checkpoints_against_crt_reference(gpu, shape, substrate, prec
     api = _api()
     plan = api.Plan(shape, substrate=substrate, precision=precision)
     prec = 0 if precision == "fp64" else 1
-    moduli = K.MODULI_FP64 if prec == 0 else K.MODULI_FP32
+    moduli = plan.info()["moduli"]
     x = inputs.uniform(shape, 0, np.complex128 if prec == 0 else np.complex64)
     xt = torch.from_numpy(x).to(gpu)
     pq = _pq(plan)

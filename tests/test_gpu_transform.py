@@ -74,13 +74,14 @@ def test_forward_small_shapes_bit_exact(gpu, shape, pq, substrate):
 def test_stage_residue_tap_matches_oracle_integers(gpu, substrate):
     """The canonical residues R_i, I_i of every stage output equal (exact integer) mod m_i."""
     api = _api()
-    from oracle import constants as K
     shape = (4, 4, 32)
     x = inputs.uniform(shape, 3)
     plan = api.Plan(shape, substrate=substrate)
     p, q = plan.info()["p"][2], plan.info()["q"][2]
+    mods = plan.info()["moduli"]
     xt = torch.from_numpy(x).to(gpu)
     r = 12
+    assert len(mods) == r
     taps = torch.zeros((x.size, 2, r), dtype=torch.int16, device=gpu)
     y1 = plan.stage(2, 1, xt, residues=taps)
     taps2 = torch.zeros((x.size, 2, r), dtype=torch.int16, device=gpu)
@@ -97,7 +98,7 @@ def test_stage_residue_tap_matches_oracle_integers(gpu, substrate):
         s2 = ox.line_stage(s1["out"], 32, p, q, 2)
         assert np.array_equal(y2h[line], s2["out"])
         for slot in range(32):
-            for k, m in enumerate(K.MODULI_FP64):
+            for k, m in enumerate(mods):
                 assert t1[line, slot, 0, k] == s1["re"][slot] % m
                 assert t1[line, slot, 1, k] == s1["im"][slot] % m
                 assert t2[line, slot, 0, k] == s2["re"][slot] % m
@@ -132,14 +133,19 @@ def test_extreme_magnitudes_bit_exact(gpu, kind):
 
 @pytest.mark.parametrize("substrate", ["fp16", "int8", "fp8"])
 def test_permuted_modulus_set_gives_identical_bits(gpu, substrate):
-    """The reconstructed integers do not depend on the modulus order (any
-    admissible set has the capacity, Eq. capacity), so a permuted set must
-    reproduce the default plan's output bit for bit; for FP16 it moves
-    different moduli onto the limb-split and single-slot paths."""
+    """The reconstructed integers do not depend on the modulus set (any
+    admissible set has the capacity, Eq. capacity), so another set must
+    reproduce the default plan's output bit for bit: on INT8 and FP8 the
+    paper's set, permuted (three-digit FP8 moduli, so the general FP8 tile);
+    on FP16, whose single-slot residue GEMM takes moduli up to 1024, the
+    default set reversed."""
     api = _api()
     shape = (8, 24, 32)
     x = inputs.uniform(shape, 12)
-    mods = [2039, 2029, 2027, 1089, 1024, 487, 491, 511, 529, 625, 841, 961]
+    if substrate == "fp16":
+        mods = [967, 971, 977, 983, 991, 997, 1009, 1013, 1019, 1021, 1023, 1024]
+    else:
+        mods = [2039, 2029, 2027, 1089, 1024, 487, 491, 511, 529, 625, 841, 961]
     y0 = _run(api.Plan(shape), x, gpu)
     y1 = _run(api.Plan(shape, substrate=substrate, moduli=mods), x, gpu)
     assert np.array_equal(y0, y1)
@@ -229,9 +235,9 @@ def test_fp8_full_length_tile_bit_exact(gpu, precision):
 
 
 def test_fp8_general_tile_at_k32(gpu):
-    """A modulus set outside the full-length tile's digit rule (1089, three
-    digits, after the split) runs the general FP8 tile at K = 32: the same
-    bits as the default plan."""
+    """A modulus set outside the full-length tile's digit rule (the paper's
+    set reordered: its moduli above 1052 take three FP8 digits) runs the
+    general FP8 tile at K = 32: the same bits as the default plan."""
     api = _api()
     shape = (2, 8, 1024)
     x = inputs.uniform(shape, 14)

@@ -106,23 +106,22 @@ def test_group_block_option_is_validated():
         assert e.value.status == 1, gb
 
 
-def test_fp16_substrate_rejects_a_large_modulus_past_the_split():
-    """FP16 takes one slot per index for moduli 4.. of an FP64 set, which is
-    exact only when 64 h (h + e) <= 2^24 (h = floor(m/2); e = 0 for a power
-    of two, whose residues are exact, else 2): 1024 and 961 pass, 1089 at
-    index 5 violates it."""
+def test_fp16_substrate_rejects_a_modulus_above_the_single_slot_bound():
+    """With the reciprocal reduction FP16 takes one slot per index for every
+    modulus of a set, which is exact only when 64 h (h + e) <= 2^24 (h =
+    floor(m/2); e = 0 for a power of two, whose residues are exact, else 2):
+    1023 and 1024 pass, 1089 does not, nor do the paper's moduli above 2000."""
     from paper_2606_23698_amd import api
     from paper_2606_23698_amd._lib import ObfftError
     h = 1089 // 2
     assert 64 * h * (h + 2) > 2 ** 24
-    h = 961 // 2
+    h = 1023 // 2
     assert 64 * h * (h + 2) <= 2 ** 24
     assert 64 * 512 * 512 == 2 ** 24          # m = 1024: exactly at the bound
-    mods = [2039, 2029, 2027, 961, 1024, 1089, 841, 625, 529, 511, 491, 487]
-    assert sorted(mods) == sorted(K.MODULI_FP64)
-    with pytest.raises(ObfftError) as e:
-        api.Plan((32, 32, 32), substrate="fp16", moduli=mods)
-    assert e.value.status == 2   # OBFFT_UNSUPPORTED_SIZE
+    for mods in ([1024, 1089, 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967], list(K.MODULI_FP64)):
+        with pytest.raises(ObfftError) as e:
+            api.Plan((32, 32, 32), substrate="fp16", moduli=mods)
+        assert e.value.status == 2, mods   # OBFFT_UNSUPPORTED_SIZE
 
 
 def test_status_strings_and_taps_layout():
