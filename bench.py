@@ -31,7 +31,7 @@ SUB_NAME = {0: "fp8", 1: "int8", 2: "fp16"}
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters in
 # profiles/ob_stage_kernel_fp16_1024cubed_counters.md; valid only for the
 # kernel sources they were taken with (fingerprint below), else null.
-TRAFFIC_MEASURED = {"bytes": 34.610e9, "sources_sha256_16": "accd6b20464b83de"}
+TRAFFIC_MEASURED = {"bytes": 34.610e9, "sources_sha256_16": "74bd6d6a25ee0a68"}
 KERNEL_SOURCES = ["paper_2606_23698_amd/csrc/ob_kernels.hip", "paper_2606_23698_amd/csrc/ob_stage.h",
                   "paper_2606_23698_amd/csrc/ob_device.h", "paper_2606_23698_amd/csrc/ob_recon.h",
                   "paper_2606_23698_amd/csrc/obfft_internal.h"]

@@ -198,8 +198,16 @@ __device__ __forceinline__ void put_slots16(unsigned char* form_base, int jc, in
     *(uint32_t*)(form_base + f16_slot1<NT>(jc, s0)) =
         __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r[0], r[1]));
   } else {
+    // one 16-bit store per index (three indices may straddle two lanes).  The
+    // conversion goes through the packing instruction: a plain cast of a value
+    // computed in FP64 became a software double-to-half conversion of some
+    // twenty instructions (the residues are small integers, exact either way).
 #pragma unroll
-    for (int u = 0; u < KQ; u++) *(_Float16*)(form_base + f16_slot1<NT>(jc, s0 + u)) = (_Float16)r[u];
+    for (int u = 0; u < KQ; u += 2) {
+      const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r[u], u + 1 < KQ ? r[u + 1] : 0.0f));
+      *(uint16_t*)(form_base + f16_slot1<NT>(jc, s0 + u)) = (uint16_t)w;
+      if (u + 1 < KQ) *(uint16_t*)(form_base + f16_slot1<NT>(jc, s0 + u + 1)) = (uint16_t)(w >> 16);
+    }
   }
 }
 
