@@ -131,6 +131,23 @@ def test_extreme_magnitudes_bit_exact(gpu, kind):
     assert rel_l2(y, hi, lo) <= 1e-14
 
 
+def test_default_modulus_sets(gpu):
+    """Transform plans default to the sets of moduli at most 1024; the H0
+    reduction, which needs reduction-friendly moduli, to the paper's set."""
+    from oracle import constants as K
+    api = _api()
+    shape = (8, 8, 16)
+    info = api.Plan(shape).info()
+    assert info["moduli"] == [1024, 1023, 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967]
+    assert info["S"] == 15 and info["S_frac"] == 6 and info["log2M"] > info["budget_bits"]
+    assert info["substrate"] == 2   # FP16 under substrate auto
+    info32 = api.Plan(shape, precision="fp32").info()
+    assert info32["moduli"] == [1024, 1023, 1021, 1019, 1013, 1009] and info32["S"] == 8
+    assert api.Plan(shape, reduction="h0").info()["moduli"] == list(K.MODULI_FP64)
+    # the paper's set on substrate auto runs on INT8 (it exceeds the FP16 single-slot bound)
+    assert api.Plan(shape, moduli=list(K.MODULI_FP64)).info()["substrate"] == 1
+
+
 @pytest.mark.parametrize("substrate", ["fp16", "int8", "fp8"])
 def test_permuted_modulus_set_gives_identical_bits(gpu, substrate):
     """The reconstructed integers do not depend on the modulus set (any

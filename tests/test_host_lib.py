@@ -51,6 +51,29 @@ def test_plan_crt_constants_equal_oracle(precision, mods):
     assert c["S"] == K.n_slices(mods) and c["S_frac"] == K.n_frac_slices(mods)
 
 
+# The transform plans' default modulus sets (every modulus at most 1024).
+STAGE_FP64 = [1024, 1023, 1021, 1019, 1013, 1009, 997, 991, 983, 977, 971, 967]
+STAGE_FP32 = [1024, 1023, 1021, 1019, 1013, 1009]
+
+
+@pytest.mark.parametrize("mods,k", [(STAGE_FP64, 53), (STAGE_FP32, 24)])
+def test_default_stage_sets_are_admissible(mods, k):
+    """The default sets of the transform plans, checked by the oracle's own
+    definitions: pairwise coprime, the capacity of Eq. capacity at the
+    longest contraction (K = 32), every modulus inside the FP16 single-slot
+    bound 64 h (h + e) <= 2^24, and the epilogue shape of the paper's sets
+    (15 / 8 byte slices of u_k, 6 of w_k), which the kernels compile in."""
+    assert K.pairwise_coprime(mods)
+    assert K.capacity_ok(mods, 32, k)
+    for m in mods:
+        h = m // 2
+        e = 0 if m & (m - 1) == 0 else 2
+        assert 64 * h * (h + e) <= 2 ** 24, m
+    paper = K.MODULI_FP64 if k == 53 else K.MODULI_FP32
+    assert K.n_slices(mods) == K.n_slices(paper)
+    assert K.n_frac_slices(mods) == K.n_frac_slices(paper) == 6
+
+
 def test_capacity_budget_rejects_rev33():
     from paper_2606_23698_amd import api
     from paper_2606_23698_amd._lib import ObfftError
